@@ -1,0 +1,153 @@
+// C-ABI entry points (include/pbmp.h).  Every call converts library errors
+// into status codes and a per-context message.
+#include <cstring>
+
+#include "runtime.hpp"
+
+using pbmp::Error;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+template <class F> int guarded(pbmp_ctx *c, F &&f) {
+  if (!c) return PBMP_EARG;
+  try {
+    int rc = f();
+    if (rc == 0) c->err.clear();
+    return rc;
+  } catch (const Error &e) {
+    c->err = e.what();
+    return e.code;
+  } catch (const std::exception &e) {
+    c->err = e.what();
+    return PBMP_EHIP;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void pbmp_default_options(pbmp_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->eps_in = 1.0;
+  o->eps_out = 80.0;
+  o->kappa = 0.125;
+  o->gauss_far = 3;
+  o->near_eta = 2.0;
+  o->mode = PBMP_MODE_AUTO;
+  o->theta = 0.5;
+  o->order_P = 4;
+  o->leaf_panels = 300;
+  o->gmres_restart = 50;
+  o->gmres_tol = 1e-6;
+  o->gmres_maxit = 1000;
+  o->scf_tol_debye = 1e-6;
+  o->scf_omega = 0.7;
+  o->scf_maxit = 200;
+  o->thole_a = 0.39;
+  o->precision = PBMP_MIXED;
+  o->hip_stream = nullptr;
+}
+
+int pbmp_create(const pbmp_options *o, pbmp_ctx **out) {
+  if (!o || !out) return PBMP_EARG;
+  *out = nullptr;
+  try {
+    auto *c = new pbmp_ctx();
+    c->rt.reset(new pbmp::Runtime(*o));
+    *out = c;
+    return PBMP_OK;
+  } catch (const Error &e) {
+    g_create_error = e.what();
+    return e.code;
+  } catch (const std::exception &e) {
+    g_create_error = e.what();
+    return PBMP_EHIP;
+  }
+}
+
+int pbmp_set_mesh(pbmp_ctx *c, int64_t nv, const double *verts, int64_t nt,
+                  const int32_t *tris, int where) {
+  return guarded(c, [&] {
+    c->rt->set_mesh(nv, verts, nt, tris, where);
+    return 0;
+  });
+}
+
+int pbmp_set_sites(pbmp_ctx *c, int64_t m, const double *xyz, const double *q,
+                   const double *d, const double *Q9, const double *alpha,
+                   const int32_t *group, int where) {
+  return guarded(c, [&] {
+    c->rt->set_sites(m, xyz, q, d, Q9, alpha, group, where);
+    return 0;
+  });
+}
+
+int pbmp_solve(pbmp_ctx *c, pbmp_result *r) {
+  return guarded(c, [&] { return c->rt->solve(r); });
+}
+
+int pbmp_matvec(pbmp_ctx *c, const double *x, double *y, int transpose, int where) {
+  return guarded(c, [&] {
+    c->rt->matvec_user(x, y, transpose, where);
+    return 0;
+  });
+}
+
+int pbmp_rhs(pbmp_ctx *c, const double *p_total, double *f, int where) {
+  return guarded(c, [&] {
+    c->rt->rhs_user(p_total, f, where);
+    return 0;
+  });
+}
+
+int pbmp_site_fields(pbmp_ctx *c, const double *x, double *out, int where) {
+  return guarded(c, [&] {
+    c->rt->site_fields_user(x, out, where);
+    return 0;
+  });
+}
+
+int pbmp_backward(pbmp_ctx *c, double dG_bar, double *g_xyz, double *g_q,
+                  double *g_d, double *g_Q9, double *g_verts, int where) {
+  return guarded(c, [&] {
+    return c->rt->backward(dG_bar, g_xyz, g_q, g_d, g_Q9, g_verts, where);
+  });
+}
+
+int pbmp_kernel_stats(pbmp_ctx *c, int mode, pbmp_kstats *out) {
+  return guarded(c, [&] {
+    auto &k = c->rt->clock;
+    if (mode == 1) {
+      k.reset();
+      k.on = true;
+    } else if (mode == 0) {
+      k.on = false;
+    }
+    k.resolve();
+    if (out) {
+      out->p2p_ms = k.p2p_ms;
+      out->m2p_ms = k.m2p_ms;
+      out->p2m_ms = k.p2m_ms;
+      out->matvec_ms = k.matvec_ms;
+      out->p2p_launches = k.p2p_launches;
+      out->m2p_launches = k.m2p_launches;
+      out->matvec_calls = k.matvec_calls;
+      out->p2p_pairs = k.p2p_pairs;
+      out->m2p_pairs = k.m2p_pairs;
+    }
+    return 0;
+  });
+}
+
+const char *pbmp_last_error(const pbmp_ctx *c) {
+  if (!c) return g_create_error.c_str();
+  return c->err.c_str();
+}
+
+void pbmp_destroy(pbmp_ctx *c) { delete c; }
+
+}  // extern "C"

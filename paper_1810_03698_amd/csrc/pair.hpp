@@ -1,0 +1,89 @@
+// Far-field pair terms of the four boundary-integral kernels, shared by the
+// forward and transposed source-target products and by the near/self
+// correction.  The correction subtracts exactly the value the product added
+// (same inputs, same operation sequence, no contraction), so that for tiny
+// panels the rounding of the pair terms cancels instead of being amplified
+// by 1/r^3.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pbmp {
+
+// FP32 floor on r^2 (r >= 1e-4 A): pairs that close only occur between a
+// panel and itself or a near neighbour, whose coarse value is removed again
+// by the correction; it keeps coincident FP32 points finite.
+constexpr float kMinR2f = 1e-8f;
+
+// Adds one far-field node's terms for the difference R = p - y = (dx,dy,dz):
+// vl += 1/r, vy += e^{-k r}/r, kl += 1/r^3, ky += (1 + k r) e^{-k r}/r^3.
+// nk = -k log2(e).
+__device__ __forceinline__ void node_terms(float dx, float dy, float dz,
+                                           float kappa, float nk, float &vl,
+                                           float &vy, float &kl, float &ky) {
+#pragma clang fp contract(off)
+  const float rr = fmaxf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), kMinR2f);
+  const float ri = __builtin_amdgcn_rsqf(rr);
+  const float r = rr * ri;
+  const float ek = __builtin_amdgcn_exp2f(nk * r);
+  const float er = ek * ri;
+  const float ri2 = ri * ri;
+  vl = vl + ri;
+  vy = vy + er;
+  kl = fmaf(ri2, ri, kl);
+  ky = fmaf(fmaf(kappa, r, 1.0f), er * ri2, ky);
+}
+
+__device__ __forceinline__ void node_terms(double dx, double dy, double dz,
+                                           double kappa, double, double &vl,
+                                           double &vy, double &kl, double &ky) {
+#pragma clang fp contract(off)
+  const double rr = dx * dx + dy * dy + dz * dz;
+  const double rad = sqrt(rr);
+  const double ri = 1.0 / rad;
+  const double ek = exp(-kappa * rad);
+  const double ri3 = ri / rr;
+  vl = vl + ri;
+  vy = vy + ek * ri;
+  kl = kl + ri3;
+  ky = ky + (1.0 + kappa * rad) * ek * ri3;
+}
+
+// n.(p - y0): the nodes of a flat panel share its plane, so this is n.R
+// for every node; taken from the difference vector (error eps |p - y0|).
+__device__ __forceinline__ float normal_dist(float nx, float ny, float nz,
+                                             float dx, float dy, float dz) {
+#pragma clang fp contract(off)
+  return fmaf(nx, dx, fmaf(ny, dy, nz * dz));
+}
+
+__device__ __forceinline__ double normal_dist(double nx, double ny, double nz,
+                                              double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+  return nx * dx + ny * dy + nz * dz;
+}
+
+// Sums of one panel (nf nodes from a 16-word record) at target p, as the
+// products weight them: out = (vl, n.R kl, vy, n.R ky) before the strengths.
+template <class T>
+__device__ __forceinline__ void panel_terms(const T *rec, int nf, T px, T py,
+                                            T pz, T kappa, T nk, T out[4]) {
+  T vl = T(0), vy = T(0), kl = T(0), ky = T(0);
+  T d0[3] = {T(0), T(0), T(0)};
+  for (int q = 0; q < nf; ++q) {
+    const T dx = px - rec[3 * q], dy = py - rec[3 * q + 1], dz = pz - rec[3 * q + 2];
+    if (q == 0) {
+      d0[0] = dx;
+      d0[1] = dy;
+      d0[2] = dz;
+    }
+    node_terms(dx, dy, dz, kappa, nk, vl, vy, kl, ky);
+  }
+  const T nR = normal_dist(rec[9], rec[10], rec[11], d0[0], d0[1], d0[2]);
+  out[0] = vl;
+  out[1] = nR * kl;
+  out[2] = vy;
+  out[3] = nR * ky;
+}
+
+}  // namespace pbmp

@@ -1,0 +1,133 @@
+// Context of the pbmp library: device-resident mesh, site and solver state.
+#pragma once
+
+#include <chrono>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "tree.hpp"
+
+struct pbmp_ctx;
+
+namespace pbmp {
+
+// Accumulated device time per kernel class, when enabled.  Each timed
+// launch is bracketed by two HIP events on the launch stream; the events are
+// only resolved (synchronised and summed) when the totals are read, so the
+// accounting does not serialise the stream.
+struct KernelClock {
+  enum Kind { P2P = 0, M2P = 1, P2M = 2 };
+  bool on = false;
+  double p2p_ms = 0, m2p_ms = 0, p2m_ms = 0, near_ms = 0, matvec_ms = 0;
+  long p2p_launches = 0, m2p_launches = 0, matvec_calls = 0;
+  double p2p_pairs = 0, m2p_pairs = 0;  // executed interactions
+  struct Pending {
+    hipEvent_t a, b;
+    int kind;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t begin(hipStream_t s);
+  void end(hipStream_t s, hipEvent_t a, int kind, double pairs);
+  void resolve();
+  void reset();
+  ~KernelClock();
+};
+
+class Runtime {
+ public:
+  explicit Runtime(const pbmp_options &o);
+  ~Runtime();
+
+  void set_mesh(int64_t nv, const double *verts, int64_t nt, const int32_t *tris,
+                int where);
+  void set_sites(int64_t m, const double *xyz, const double *q, const double *d,
+                 const double *Q9, const double *alpha, const int32_t *group,
+                 int where);
+  int solve(pbmp_result *r);
+  void matvec_user(const double *x, double *y, int transpose, int where);
+  void rhs_user(const double *p, double *f, int where);
+  void site_fields_user(const double *x, double *out, int where);
+  int backward(double dGbar, double *g_xyz, double *g_q, double *g_d,
+               double *g_Q, double *g_verts, int where);
+
+  std::string err;
+  KernelClock clock;
+  pbmp_options o;
+
+ private:
+  hipStream_t s_ = nullptr;
+  bool own_stream_ = false;
+  RuleArgs ru_{};
+  bool fp64() const { return o.precision == PBMP_FP64; }
+  bool use_tree() const { return tree_active_; }
+
+  // ---- mesh (internal panel order) ----
+  int N_ = 0, Nv_ = 0;
+  std::vector<int> perm_;  // internal -> user panel index
+  Dbuf<int> d_perm_;
+  Dbuf<double> verts_;
+  Dbuf<int> tri_;
+  Dbuf<double> geo_, src64_;
+  Dbuf<float> src32_, tgt32_;
+  std::vector<double> h_geo_;
+  std::vector<double> h_verts_;
+  std::vector<int> h_tri_;  // internal order
+  Dbuf<int> nrow_, ncol_;
+  Dbuf<double> nval_, diag_;
+  Dbuf<int> trow_, tcol_;  // transposed near structure (entry ids)
+  Dbuf<int> tent_;
+  bool tree_active_ = false;
+  std::unique_ptr<Tree> tree_;
+
+  // ---- sites ----
+  int M_ = 0;
+  Dbuf<double> sxyz_, sq_, sd_, sQ_, salpha_;
+  Dbuf<int> sgroup_, srow_, scol_;
+  std::vector<double> h_sxyz_;
+
+  // ---- work ----
+  Dbuf<double> part_, rpart_;
+  int p2p_chunks_ = 1, ro_chunks_ = 1;
+  Dbuf<double> V_, w_, z_, ax_, b_, x_, hbuf_, partial_, ybuf_, tmp_;
+  Dbuf<double> mu_d_, mu_v_, Eperm_, Eind_, reac_, ind_, p_, f_, dmu2_, e_;
+  Dbuf<double> io_a_, io_b_;  // permutation staging
+  bool solved_ = false;
+  int gmres_iters_ = 0, matvecs_ = 0;
+  double last_relres_ = 0.0;
+  double t_matvec_ms_ = 0.0;
+  double t_setup_ms_ = 0.0;
+  bool setup_reported_ = false;
+
+  void sync();
+  void build_near_lists();
+  void build_site_lists();
+  void alloc_work();
+  // y = A x (internal order, device)
+  void apply(const double *x, double *y);
+  void apply_transpose(const double *x, double *y);
+  // GMRES on A x = b (device, internal order), x holds the initial guess.
+  int gmres(const double *b, double *x, bool transpose, int *iters);
+  // readout at the sites for surface solution x (internal): out [M*nout]
+  void readout(const double *x, bool full, double *out);
+  // induced-dipole loop; solvent=false: vacuum.  Returns iterations (<0:
+  // not converged).
+  int scf(bool solvent, double *mu, int *gm_warn);
+  void to_internal(const double *user, double *dev, int blocks, int where);
+  void to_user(const double *dev, double *user, int blocks, int where);
+  friend struct Backward;
+};
+
+// Physical constants (CODATA 2018; e, N_A exact)
+double coulomb_kcal();      // e^2 N_A / (4 pi eps0 1 A) in kcal/mol
+double debye_per_e_ang();   // 1 e*A in Debye
+
+}  // namespace pbmp
+
+struct pbmp_ctx {
+  std::unique_ptr<pbmp::Runtime> rt;
+  std::string err;
+};
