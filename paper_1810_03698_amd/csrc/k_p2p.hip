@@ -41,7 +41,7 @@ __global__ void k_pack_strengths(int N, int nf, const double *__restrict__ geo,
   src32[16 * (size_t)j + 14] = (float)sk;
 }
 
-template <int NF, int TPT>
+template <int NF, int TPT, bool FLOOR>
 __global__ __launch_bounds__(kBlock) void k_p2p_f32(
     const float4 *__restrict__ src, int N, const float *__restrict__ tgt,
     int Nt, int chunk, float kappa, float nk_log2e, double *__restrict__ part) {
@@ -82,7 +82,9 @@ __global__ __launch_bounds__(kBlock) void k_p2p_f32(
       const float yz[3] = {r0.z, r1.y, r2.x};
 #pragma unroll
       for (int k = 0; k < TPT; ++k) {
-        float vl = 0.f, vy = 0.f, kl = 0.f, ky = 0.f;
+        // single layer accumulated per node with the strength; double layer
+        // per panel (shared n.R): kl = sum 1/r^3, A = sum e/r^3, B = sum e/r^2
+        float kl = 0.f, A = 0.f, B = 0.f;
         float d0x = 0.f, d0y = 0.f, d0z = 0.f;
 #pragma unroll
         for (int q = 0; q < NF; ++q) {
@@ -92,14 +94,19 @@ __global__ __launch_bounds__(kBlock) void k_p2p_f32(
             d0y = dy;
             d0z = dz;
           }
-          node_terms(dx, dy, dz, kappa, nk_log2e, vl, vy, kl, ky);
+          float ri, er;
+          node_core<FLOOR>(dx, dy, dz, nk_log2e, ri, er);
+          const float ri2 = ri * ri;
+          a[k][0] = fmaf(r3.y, ri, a[k][0]);
+          a[k][2] = fmaf(r3.y, er, a[k][2]);
+          kl = fmaf(ri2, ri, kl);
+          A = fmaf(er, ri2, A);
+          B = fmaf(er, ri, B);
         }
         const float nR = normal_dist(r2.y, r2.z, r2.w, d0x, d0y, d0z);
         const float skn = r3.z * nR;
-        a[k][0] = fmaf(r3.y, vl, a[k][0]);
         a[k][1] = fmaf(skn, kl, a[k][1]);
-        a[k][2] = fmaf(r3.y, vy, a[k][2]);
-        a[k][3] = fmaf(skn, ky, a[k][3]);
+        a[k][3] = fmaf(skn, fmaf(kappa, B, A), a[k][3]);
       }
     }
 #pragma unroll
@@ -252,7 +259,7 @@ void launch_pack_strengths(hipStream_t s, int N, int nf, const double *geo,
 void launch_p2p_direct(hipStream_t s, bool fp64, int nf, int N, int Nt,
                        const double *src64, const float *src32,
                        const double *geo, const float *tgt32, double kappa,
-                       int nchunk, double *part) {
+                       int nchunk, double *part, bool floor_r2) {
   const int chunk = (N + nchunk - 1) / nchunk;
   if (fp64) {
     dim3 grid((Nt + kBlock - 1) / kBlock, nchunk);
@@ -267,14 +274,15 @@ void launch_p2p_direct(hipStream_t s, bool fp64, int nf, int N, int Nt,
     dim3 grid((Nt + kBlock * TPT - 1) / (kBlock * TPT), nchunk);
     const float kf = (float)kappa;
     const float nk = (float)(-kappa * 1.4426950408889634);
-    if (nf == 3)
-      hipLaunchKernelGGL((k_p2p_f32<3, TPT>), grid, dim3(kBlock), 0, s,
-                         reinterpret_cast<const float4 *>(src32), N, tgt32, Nt,
-                         chunk, kf, nk, part);
-    else
-      hipLaunchKernelGGL((k_p2p_f32<1, TPT>), grid, dim3(kBlock), 0, s,
-                         reinterpret_cast<const float4 *>(src32), N, tgt32, Nt,
-                         chunk, kf, nk, part);
+    const float4 *s4 = reinterpret_cast<const float4 *>(src32);
+#define PBMP_P2P(NFV, FL)                                                      \
+  hipLaunchKernelGGL((k_p2p_f32<NFV, TPT, FL>), grid, dim3(kBlock), 0, s, s4, N, \
+                     tgt32, Nt, chunk, kf, nk, part)
+    if (nf == 3 && floor_r2) PBMP_P2P(3, true);
+    else if (nf == 3) PBMP_P2P(3, false);
+    else if (floor_r2) PBMP_P2P(1, true);
+    else PBMP_P2P(1, false);
+#undef PBMP_P2P
   }
   PBMP_HIP(hipGetLastError());
 }

@@ -73,93 +73,116 @@ __device__ inline int xcd_task(int ntasks) {
 }
 
 // ---------------------------------------------------------------- P2M
-// One block per leaf; thread k owns coefficient k.  exps [3*NC].
-__global__ __launch_bounds__(64) void k_p2m(int NC, int nf,
-                                            const int *__restrict__ leaves,
-                                            const int *__restrict__ range,
-                                            const double *__restrict__ center,
-                                            const int *__restrict__ exps,
-                                            const double *__restrict__ src,
-                                            double *__restrict__ mom) {
-  constexpr int kT = 32;
-  __shared__ double sh[kT * 16];
+// One 256-lane block per leaf; every lane takes nodes of the leaf, builds
+// all monomials h^k incrementally (each from its parent multi-index) and
+// accumulates both moment sets in registers; then a wave reduction
+// (shuffles) and an LDS reduction across the four waves.
+template <int P>
+__global__ __launch_bounds__(256) void k_p2m(int nf, const int *__restrict__ leaves,
+                                             const int *__restrict__ range,
+                                             const double *__restrict__ center,
+                                             const double *__restrict__ src,
+                                             double *__restrict__ mom) {
+  constexpr Multi<P> mi{};
+  constexpr int NC = Multi<P>::n;
+  __shared__ double red[4][2 * NC];
   const int B = leaves[blockIdx.x];
   const int s0 = range[2 * B], s1 = range[2 * B + 1];
-  const double cx = center[3 * B], cy = center[3 * B + 1], cz = center[3 * B + 2];
-  for (int k0 = 0; k0 < NC; k0 += 64) {
-    const int k = k0 + threadIdx.x;
-    const bool on = k < NC;
-    const int ex = on ? exps[3 * k] : 0, ey = on ? exps[3 * k + 1] : 0,
-              ez = on ? exps[3 * k + 2] : 0;
-    double m = 0.0, mk = 0.0;
-    for (int jt = s0; jt < s1; jt += kT) {
-      const int nj = min(kT, s1 - jt);
-      __syncthreads();
-      for (int e = threadIdx.x; e < nj * 16; e += 64) sh[e] = src[(size_t)jt * 16 + e];
-      __syncthreads();
-      if (!on) continue;
-      for (int jj = 0; jj < nj; ++jj) {
-        const double *r = sh + 16 * jj;
-        for (int q = 0; q < nf; ++q) {
-          const double h[3] = {r[3 * q] - cx, r[3 * q + 1] - cy, r[3 * q + 2] - cz};
-          double px[9], py[9], pz[9];
-          px[0] = py[0] = pz[0] = 1.0;
-          for (int t = 1; t <= 8; ++t) {
-            px[t] = px[t - 1] * h[0];
-            py[t] = py[t - 1] * h[1];
-            pz[t] = pz[t - 1] * h[2];
-          }
-          m += r[13] * px[ex] * py[ey] * pz[ez];
-          double dk = 0.0;
-          if (ex) dk += ex * r[9] * px[ex - 1] * py[ey] * pz[ez];
-          if (ey) dk += ey * r[10] * px[ex] * py[ey - 1] * pz[ez];
-          if (ez) dk += ez * r[11] * px[ex] * py[ey] * pz[ez - 1];
-          mk += r[14] * dk;
-        }
-      }
+  const double c[3] = {center[3 * B], center[3 * B + 1], center[3 * B + 2]};
+  double m[NC], mk[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) m[k] = mk[k] = 0.0;
+  const int nnode = (s1 - s0) * nf;
+  for (int g = threadIdx.x; g < nnode; g += 256) {
+    const int j = s0 + g / nf, q = g % nf;
+    const double *r = src + 16 * (size_t)j;
+    const double h[3] = {r[3 * q] - c[0], r[3 * q + 1] - c[1], r[3 * q + 2] - c[2]};
+    const double n[3] = {r[9], r[10], r[11]};
+    const double sv = r[13], sk = r[14];
+    double mono[NC];
+    mono[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k < NC; ++k) {
+      const int d = mi.e[k][0] ? 0 : (mi.e[k][1] ? 1 : 2);
+      mono[k] = mono[mi.m1[k][d]] * h[d];
     }
-    if (on) {
-      mom[(size_t)B * 2 * NC + k] = m;
-      mom[(size_t)B * 2 * NC + NC + k] = mk;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      m[k] += sv * mono[k];
+      double dk = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        if (mi.m1[k][d] >= 0) dk += mi.e[k][d] * n[d] * mono[mi.m1[k][d]];
+      mk[k] += sk * dk;
     }
   }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    double a = m[k], b = mk[k];
+    for (int off = 32; off > 0; off >>= 1) {
+      a += __shfl_down(a, off, 64);
+      b += __shfl_down(b, off, 64);
+    }
+    if (lane == 0) {
+      red[wave][k] = a;
+      red[wave][NC + k] = b;
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < 2 * NC; k += 256)
+    mom[(size_t)B * 2 * NC + k] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
 }
 
 // ---------------------------------------------------------------- M2M
-__device__ inline double binom(int n, int k) {
-  double c = 1.0;
-  for (int i = 1; i <= k; ++i) c = c * (n - k + i) / i;
-  return c;
-}
-
-__global__ __launch_bounds__(64) void k_m2m(int NC, const int *__restrict__ boxes,
+// (h + t)^k = sum_{j <= k} C(k, j) t^{k-j} h^j, t = child centre - parent
+// centre; one block per parent box, one lane per coefficient.
+template <int P>
+__global__ __launch_bounds__(64) void k_m2m(const int *__restrict__ boxes,
                                             const int *__restrict__ child,
                                             const double *__restrict__ center,
-                                            const int *__restrict__ exps,
                                             double *__restrict__ mom) {
+  constexpr Multi<P> mi{};
+  constexpr int NC = Multi<P>::n;
+  __shared__ double tp[8][3][P + 1];
+  __shared__ double binom[P + 1][P + 1];
   const int B = boxes[blockIdx.x];
+  if (threadIdx.x == 0) {
+    for (int a = 0; a <= P; ++a) {
+      binom[a][0] = 1.0;
+      for (int b = 1; b <= P; ++b) binom[a][b] = (b > a) ? 0.0 : binom[a][b - 1] * (a - b + 1) / b;
+    }
+  }
+  int nch = 0;
+  for (int cc = 0; cc < 8; ++cc) nch += child[8 * B + cc] >= 0;
+  if (threadIdx.x < 3 * nch) {
+    const int cc = threadIdx.x / 3, d = threadIdx.x % 3;
+    const int C = child[8 * B + cc];
+    const double t = center[3 * C + d] - center[3 * B + d];
+    double p = 1.0;
+    for (int e = 0; e <= P; ++e) {
+      tp[cc][d][e] = p;
+      p *= t;
+    }
+  }
+  __syncthreads();
   for (int k = threadIdx.x; k < NC; k += 64) {
-    const int kx = exps[3 * k], ky = exps[3 * k + 1], kz = exps[3 * k + 2];
-    double m = 0.0, mk = 0.0;
-    for (int c = 0; c < 8; ++c) {
-      const int C = child[8 * B + c];
-      if (C < 0) break;
-      const double t[3] = {center[3 * C] - center[3 * B], center[3 * C + 1] - center[3 * B + 1],
-                           center[3 * C + 2] - center[3 * B + 2]};
-      // (h + t)^k = sum_{j <= k} C(k, j) t^{k-j} h^j
+    const int kx = mi.e[k][0], ky = mi.e[k][1], kz = mi.e[k][2];
+    double m = 0.0, mkk = 0.0;
+    for (int cc = 0; cc < nch; ++cc) {
+      const double *cm = mom + (size_t)child[8 * B + cc] * 2 * NC;
       for (int jx = 0; jx <= kx; ++jx)
         for (int jy = 0; jy <= ky; ++jy)
           for (int jz = 0; jz <= kz; ++jz) {
-            const int s = jx + jy + jz;
-            const int jdx = s * (s + 1) * (s + 2) / 6 + (s - jx) * (s - jx + 1) / 2 + (s - jx - jy);
-            const double w = binom(kx, jx) * binom(ky, jy) * binom(kz, jz) *
-                             pow(t[0], kx - jx) * pow(t[1], ky - jy) * pow(t[2], kz - jz);
-            m += w * mom[(size_t)C * 2 * NC + jdx];
-            mk += w * mom[(size_t)C * 2 * NC + NC + jdx];
+            const int jd = Multi<P>::index(jx, jy, jz);
+            const double w = binom[kx][jx] * binom[ky][jy] * binom[kz][jz] *
+                             tp[cc][0][kx - jx] * tp[cc][1][ky - jy] * tp[cc][2][kz - jz];
+            m += w * cm[jd];
+            mkk += w * cm[NC + jd];
           }
     }
     mom[(size_t)B * 2 * NC + k] = m;
-    mom[(size_t)B * 2 * NC + NC + k] = mk;
+    mom[(size_t)B * 2 * NC + NC + k] = mkk;
   }
 }
 
@@ -173,7 +196,7 @@ __global__ void k_cast(size_t n, const double *__restrict__ a, float *__restrict
 // sources = panels of the listed leaves, streamed through LDS.
 constexpr int kTileT = 128;
 
-template <class T, int NF, int TPT>
+template <class T, int NF, int TPT, bool FLOOR>
 __device__ void p2p_task_body(const T *__restrict__ src, const T *__restrict__ tgt,
                               int N, int t0, int t1, const int *__restrict__ ranges,
                               int lb, int le, T kappa, T nk, int slot,
@@ -208,13 +231,39 @@ __device__ void p2p_task_body(const T *__restrict__ src, const T *__restrict__ t
           const T *r = sh + 16 * jj;
 #pragma unroll
           for (int k = 0; k < TPT; ++k) {
-            T t4[4];
-            panel_terms<T>(r, NF, px[k], py[k], pz[k], kappa, nk, t4);
-            const T vl = t4[0], vy = t4[2];
-            a[k][0] += r[13] * vl;
-            a[k][1] += r[14] * t4[1];
-            a[k][2] += r[13] * vy;
-            a[k][3] += r[14] * t4[3];
+            if constexpr (sizeof(T) == 4) {
+              // as the direct FP32 product: single layer per node with the
+              // strength, double layer per panel through the shared n.R
+              float kl = 0.f, A = 0.f, B = 0.f, d0[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+              for (int q = 0; q < NF; ++q) {
+                const float dx = px[k] - r[3 * q], dy = py[k] - r[3 * q + 1],
+                            dz = pz[k] - r[3 * q + 2];
+                if (q == 0) {
+                  d0[0] = dx;
+                  d0[1] = dy;
+                  d0[2] = dz;
+                }
+                float ri, er;
+                node_core<FLOOR>(dx, dy, dz, nk, ri, er);
+                const float ri2 = ri * ri;
+                a[k][0] = fmaf(r[13], ri, a[k][0]);
+                a[k][2] = fmaf(r[13], er, a[k][2]);
+                kl = fmaf(ri2, ri, kl);
+                A = fmaf(er, ri2, A);
+                B = fmaf(er, ri, B);
+              }
+              const float skn = r[14] * normal_dist(r[9], r[10], r[11], d0[0], d0[1], d0[2]);
+              a[k][1] = fmaf(skn, kl, a[k][1]);
+              a[k][3] = fmaf(skn, fmaf(kappa, B, A), a[k][3]);
+            } else {
+              T t4[4];
+              panel_terms<T>(r, NF, px[k], py[k], pz[k], kappa, nk, t4);
+              a[k][0] += r[13] * t4[0];
+              a[k][1] += r[14] * t4[1];
+              a[k][2] += r[13] * t4[2];
+              a[k][3] += r[14] * t4[3];
+            }
           }
         }
 #pragma unroll
@@ -229,7 +278,7 @@ __device__ void p2p_task_body(const T *__restrict__ src, const T *__restrict__ t
   }
 }
 
-template <class T, int NF>
+template <class T, int NF, bool FLOOR>
 __global__ __launch_bounds__(64) void k_p2p_tasks(int ntask, const int *__restrict__ tasks,
                                                   const int *__restrict__ slots,
                                                   const int *__restrict__ ranges,
@@ -244,11 +293,11 @@ __global__ __launch_bounds__(64) void k_p2p_tasks(int ntask, const int *__restri
   const int slot = slots[task];
   const int tpt = min(5, (t1 - t0 + 63) / 64);
   switch (tpt) {
-    case 1: p2p_task_body<T, NF, 1>(src, tgt, N, t0, t1, ranges, lb, le, kappa, nk, slot, part, sh); break;
-    case 2: p2p_task_body<T, NF, 2>(src, tgt, N, t0, t1, ranges, lb, le, kappa, nk, slot, part, sh); break;
-    case 3: p2p_task_body<T, NF, 3>(src, tgt, N, t0, t1, ranges, lb, le, kappa, nk, slot, part, sh); break;
-    case 4: p2p_task_body<T, NF, 4>(src, tgt, N, t0, t1, ranges, lb, le, kappa, nk, slot, part, sh); break;
-    default: p2p_task_body<T, NF, 5>(src, tgt, N, t0, t1, ranges, lb, le, kappa, nk, slot, part, sh); break;
+    case 1: p2p_task_body<T, NF, 1, FLOOR>(src, tgt, N, t0, t1, ranges, lb, le, kappa, nk, slot, part, sh); break;
+    case 2: p2p_task_body<T, NF, 2, FLOOR>(src, tgt, N, t0, t1, ranges, lb, le, kappa, nk, slot, part, sh); break;
+    case 3: p2p_task_body<T, NF, 3, FLOOR>(src, tgt, N, t0, t1, ranges, lb, le, kappa, nk, slot, part, sh); break;
+    case 4: p2p_task_body<T, NF, 4, FLOOR>(src, tgt, N, t0, t1, ranges, lb, le, kappa, nk, slot, part, sh); break;
+    default: p2p_task_body<T, NF, 5, FLOOR>(src, tgt, N, t0, t1, ranges, lb, le, kappa, nk, slot, part, sh); break;
   }
 }
 
@@ -387,6 +436,29 @@ void launch_m2p(Tree &t, hipStream_t s, const T *mom, const T *tgt, int N, T kap
   }
 }
 
+template <int P> void launch_moments_p(Tree &t, hipStream_t s, int nf, const double *src64) {
+  hipLaunchKernelGGL(k_p2m<P>, dim3(t.nleaf), dim3(256), 0, s, nf, t.d_leaves.p, t.d_range.p,
+                     t.d_center.p, src64, t.d_mom64.p);
+  for (size_t l = 0; l + 1 < t.level_ptr.size(); ++l) {
+    const int nb = t.level_ptr[l + 1] - t.level_ptr[l];
+    if (nb > 0)
+      hipLaunchKernelGGL(k_m2m<P>, dim3(nb), dim3(64), 0, s, t.d_leaf_boxes.p + t.level_ptr[l],
+                         t.d_child.p, t.d_center.p, t.d_mom64.p);
+  }
+}
+
+void launch_moments(Tree &t, hipStream_t s, int nf, const double *src64) {
+  switch (t.prm.order) {
+    case 1: launch_moments_p<1>(t, s, nf, src64); break;
+    case 2: launch_moments_p<2>(t, s, nf, src64); break;
+    case 3: launch_moments_p<3>(t, s, nf, src64); break;
+    case 4: launch_moments_p<4>(t, s, nf, src64); break;
+    case 5: launch_moments_p<5>(t, s, nf, src64); break;
+    case 6: launch_moments_p<6>(t, s, nf, src64); break;
+    default: throw Error(PBMP_EARG, "treecode order must be 1..6");
+  }
+}
+
 }  // namespace
 
 void tree_upload_exponents(Tree &t, hipStream_t s) {
@@ -399,18 +471,10 @@ void tree_upload_exponents(Tree &t, hipStream_t s) {
 
 void tree_apply(Tree &t, hipStream_t s, bool fp64, int nf, int N, const double *geo,
                 const double *src64, const float *src32, const float *tgt32,
-                double kappa, double *part, KernelClock &clk) {
+                double kappa, double *part, KernelClock &clk, bool floor_r2) {
   const int NC = t.ncoef;
   hipEvent_t e0 = clk.on ? clk.begin(s) : nullptr;
-  hipLaunchKernelGGL(k_p2m, dim3(t.nleaf), dim3(64), 0, s, NC, nf, t.d_leaves.p,
-                     t.d_range.p, t.d_center.p, t.d_monos.p, src64, t.d_mom64.p);
-  for (size_t l = 0; l + 1 < t.level_ptr.size(); ++l) {
-    const int nb = t.level_ptr[l + 1] - t.level_ptr[l];
-    if (nb > 0)
-      hipLaunchKernelGGL(k_m2m, dim3(nb), dim3(64), 0, s, NC,
-                         t.d_leaf_boxes.p + t.level_ptr[l], t.d_child.p, t.d_center.p,
-                         t.d_monos.p, t.d_mom64.p);
-  }
+  launch_moments(t, s, nf, src64);
   if (!fp64) {
     const size_t n = (size_t)t.nbox * 2 * NC;
     hipLaunchKernelGGL(k_cast, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
@@ -422,25 +486,21 @@ void tree_apply(Tree &t, hipStream_t s, bool fp64, int nf, int N, const double *
   const float nk32 = (float)(-kappa * 1.4426950408889634);
   e0 = clk.on ? clk.begin(s) : nullptr;
   const int nbp = ((t.n_p2p_tasks + 7) / 8) * 8;
+#define PBMP_TP(TT, NFV, FL, SRC, TGT, KAP, NK)                                          \
+  hipLaunchKernelGGL((k_p2p_tasks<TT, NFV, FL>), dim3(nbp), dim3(64), 0, s, t.n_p2p_tasks, \
+                     t.d_p2p_task.p, t.d_p2p_slot.p, t.d_p2p_src.p, SRC, TGT, N, KAP, NK,  \
+                     part)
   if (fp64) {
-    if (nf == 3)
-      hipLaunchKernelGGL((k_p2p_tasks<double, 3>), dim3(nbp), dim3(64), 0, s, t.n_p2p_tasks,
-                         t.d_p2p_task.p, t.d_p2p_slot.p, t.d_p2p_src.p, src64, geo, N,
-                         kappa, 0.0, part);
-    else
-      hipLaunchKernelGGL((k_p2p_tasks<double, 1>), dim3(nbp), dim3(64), 0, s, t.n_p2p_tasks,
-                         t.d_p2p_task.p, t.d_p2p_slot.p, t.d_p2p_src.p, src64, geo, N,
-                         kappa, 0.0, part);
+    if (nf == 3) PBMP_TP(double, 3, true, src64, geo, kappa, 0.0);
+    else PBMP_TP(double, 1, true, src64, geo, kappa, 0.0);
   } else {
-    if (nf == 3)
-      hipLaunchKernelGGL((k_p2p_tasks<float, 3>), dim3(nbp), dim3(64), 0, s, t.n_p2p_tasks,
-                         t.d_p2p_task.p, t.d_p2p_slot.p, t.d_p2p_src.p, src32, tgt32, N,
-                         (float)kappa, nk32, part);
-    else
-      hipLaunchKernelGGL((k_p2p_tasks<float, 1>), dim3(nbp), dim3(64), 0, s, t.n_p2p_tasks,
-                         t.d_p2p_task.p, t.d_p2p_slot.p, t.d_p2p_src.p, src32, tgt32, N,
-                         (float)kappa, nk32, part);
+    const float kf = (float)kappa;
+    if (nf == 3 && floor_r2) PBMP_TP(float, 3, true, src32, tgt32, kf, nk32);
+    else if (nf == 3) PBMP_TP(float, 3, false, src32, tgt32, kf, nk32);
+    else if (floor_r2) PBMP_TP(float, 1, true, src32, tgt32, kf, nk32);
+    else PBMP_TP(float, 1, false, src32, tgt32, kf, nk32);
   }
+#undef PBMP_TP
   PBMP_HIP(hipGetLastError());
   if (clk.on) clk.end(s, e0, KernelClock::P2P, t.direct_pairs);
 

@@ -38,10 +38,12 @@ void launch_pack_strengths(hipStream_t s, int N, int nf, const double *geo,
 
 // Direct far-field sums over all panels of the source range, per target:
 // part[(chunk*4 + k)*Nt + i], k = V_L, K_L, V_Y, K_Y.
+// floor_r2: clamp FP32 distances at 1e-4 A (needed only when panels are
+// small enough for a node and a centroid to coincide in FP32).
 void launch_p2p_direct(hipStream_t s, bool fp64, int nf, int N, int Nt,
                        const double *src64, const float *src32,
                        const double *geo, const float *tgt32, double kappa,
-                       int nchunk, double *part);
+                       int nchunk, double *part, bool floor_r2 = true);
 
 // y = A x from the far partials (summed over nchunk chunks in order), the
 // near/self CSR correction and the identity terms (eq. integral_eq).
@@ -133,7 +135,8 @@ struct KernelClock;
 // accepted boxes, into part[slot][4][N].
 void tree_apply(Tree &t, hipStream_t s, bool fp64, int nf, int N,
                 const double *geo, const double *src64, const float *src32,
-                const float *tgt32, double kappa, double *part, KernelClock &clk);
+                const float *tgt32, double kappa, double *part, KernelClock &clk,
+                bool floor_r2);
 // finish with a per-target number of partial slots
 void launch_finish_slots(hipStream_t s, int N, const int *tslots,
                          const double *part, const int *rowptr, const int *col,

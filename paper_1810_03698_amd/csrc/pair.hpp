@@ -15,23 +15,33 @@ namespace pbmp {
 // by the correction; it keeps coincident FP32 points finite.
 constexpr float kMinR2f = 1e-8f;
 
-// Adds one far-field node's terms for the difference R = p - y = (dx,dy,dz):
-// vl += 1/r, vy += e^{-k r}/r, kl += 1/r^3, ky += (1 + k r) e^{-k r}/r^3.
-// nk = -k log2(e).
+// Reciprocal distance and screened reciprocal distance of one far-field
+// node for the difference R = p - y = (dx,dy,dz): ri = 1/r, er = e^{-k r}/r.
+// nk = -k log2(e).  FLOOR keeps r >= 1e-4 A.
+template <bool FLOOR = true>
+__device__ __forceinline__ void node_core(float dx, float dy, float dz, float nk,
+                                          float &ri, float &er) {
+#pragma clang fp contract(off)
+  float rr = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+  if (FLOOR) rr = fmaxf(rr, kMinR2f);
+  ri = __builtin_amdgcn_rsqf(rr);
+  const float ek = __builtin_amdgcn_exp2f(nk * (rr * ri));
+  er = ek * ri;
+}
+
+// Adds one node's terms: vl += 1/r, vy += e^{-kr}/r, kl += 1/r^3,
+// ky += (1 + k r) e^{-k r}/r^3 (as e/r^3 + k e/r^2).
 __device__ __forceinline__ void node_terms(float dx, float dy, float dz,
                                            float kappa, float nk, float &vl,
                                            float &vy, float &kl, float &ky) {
 #pragma clang fp contract(off)
-  const float rr = fmaxf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)), kMinR2f);
-  const float ri = __builtin_amdgcn_rsqf(rr);
-  const float r = rr * ri;
-  const float ek = __builtin_amdgcn_exp2f(nk * r);
-  const float er = ek * ri;
+  float ri, er;
+  node_core<true>(dx, dy, dz, nk, ri, er);
   const float ri2 = ri * ri;
   vl = vl + ri;
   vy = vy + er;
   kl = fmaf(ri2, ri, kl);
-  ky = fmaf(fmaf(kappa, r, 1.0f), er * ri2, ky);
+  ky = fmaf(er, ri2, fmaf(kappa * er, ri, ky));
 }
 
 __device__ __forceinline__ void node_terms(double dx, double dy, double dz,

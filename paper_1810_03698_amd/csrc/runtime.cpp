@@ -312,6 +312,28 @@ void Runtime::set_mesh(int64_t nv, const double *verts, int64_t nt,
   for (int j = 0; j < N; ++j)
     PBMP_REQUIRE(h_geo_[6 * (size_t)N + j] > 1e-12, PBMP_EMESH,
                  "panel with area <= 1e-12 A^2");
+  // Far nodes are interior: a node lies at least (smallest altitude)/6 from
+  // its panel's boundary, hence from every other panel's centroid.  When
+  // that exceeds 1e-4 A plus the FP32 rounding of the coordinates, no FP32
+  // pair distance can fall below the floor and the product may skip it.
+  {
+    double min_alt = 1e300, max_abs = 0.0;
+    for (int j = 0; j < N; ++j) {
+      const int *t = &h_tri_[3 * (size_t)j];
+      double len2 = 0.0;
+      for (int e = 0; e < 3; ++e) {
+        const double *a = &hv[3 * t[e]], *b = &hv[3 * t[(e + 1) % 3]];
+        double l2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+          l2 += (a[d] - b[d]) * (a[d] - b[d]);
+          max_abs = std::max(max_abs, std::fabs(a[d]));
+        }
+        len2 = std::max(len2, l2);
+      }
+      min_alt = std::min(min_alt, 2.0 * h_geo_[6 * (size_t)N + j] / std::sqrt(len2));
+    }
+    floor_r2_ = !(min_alt / 6.0 > 1e-4 + 1e-6 * max_abs);
+  }
   build_near_lists();
   // --- tree
   tree_active_ = (o.mode == PBMP_MODE_TREECODE) ||
@@ -506,9 +528,19 @@ void Runtime::build_site_lists() {
     col.insert(col.end(), tmp.begin(), tmp.end());
     row[l + 1] = (int)col.size();
   }
+  // per panel: the sites for which it is near (transposed lists)
+  std::vector<int> trow(N + 1, 0), tcol(std::max<size_t>(1, col.size()), 0);
+  for (int l = 0; l < M; ++l)
+    for (int e = row[l]; e < row[l + 1]; ++e) trow[col[e] + 1]++;
+  for (int j = 0; j < N; ++j) trow[j + 1] += trow[j];
+  std::vector<int> fill(trow.begin(), trow.end() - 1);
+  for (int l = 0; l < M; ++l)
+    for (int e = row[l]; e < row[l + 1]; ++e) tcol[fill[col[e]]++] = l;
   if (col.empty()) col.push_back(0);  // keep a valid allocation
   srow_.upload(row.data(), row.size(), s_);
   scol_.upload(col.data(), col.size(), s_);
+  tsrow_.upload(trow.data(), trow.size(), s_);
+  tscol_.upload(tcol.data(), tcol.size(), s_);
   sync();
 }
 
@@ -518,13 +550,13 @@ void Runtime::apply(const double *x, double *y) {
   launch_pack_strengths(s_, N, ru_.nf, geo_.p, x, src64_.p, src32_.p);
   if (use_tree()) {
     tree_apply(*tree_, s_, fp64(), ru_.nf, N, geo_.p, src64_.p, src32_.p,
-               tgt32_.p, o.kappa, part_.p, clock);
+               tgt32_.p, o.kappa, part_.p, clock, floor_r2_);
     launch_finish_slots(s_, N, tree_->d_tslots.p, part_.p, nrow_.p, ncol_.p,
                         nval_.p, x, o.eps_in / o.eps_out, y);
   } else {
     hipEvent_t e0 = clock.on ? clock.begin(s_) : nullptr;
     launch_p2p_direct(s_, fp64(), ru_.nf, N, N, src64_.p, src32_.p, geo_.p,
-                      tgt32_.p, o.kappa, p2p_chunks_, part_.p);
+                      tgt32_.p, o.kappa, p2p_chunks_, part_.p, floor_r2_);
     if (clock.on) clock.end(s_, e0, KernelClock::P2P, (double)N * N * ru_.nf);
     launch_finish(s_, N, p2p_chunks_, part_.p, nrow_.p, ncol_.p, nval_.p, x,
                   o.eps_in / o.eps_out, y);
@@ -560,12 +592,7 @@ int Runtime::gmres(const double *b, double *x, bool transpose, int *iters) {
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hh(3 * (m + 2)), y(m);
   int it = 0;
   while (true) {
-    if (transpose) {
-      // A^T acts on x directly (no preconditioner for the adjoint solve)
-      op(x, ax_.p);
-    } else {
-      op(x, ax_.p);
-    }
+    op(x, ax_.p);
     launch_xmy(s_, n, b, ax_.p, w_.p);
     const double beta = std::sqrt(dot_host(w_.p, w_.p));
     last_relres_ = beta / bnorm;
@@ -577,12 +604,11 @@ int Runtime::gmres(const double *b, double *x, bool transpose, int *iters) {
     int k_done = 0;
     for (int k = 0; k < m; ++k) {
       double *vk = V_.p + (size_t)k * ld;
-      if (transpose) {
-        op(vk, w_.p);
-      } else {
+      if (transpose)
+        precond_T(vk, z_.p);
+      else
         launch_precond(s_, N, diag_.p, o.eps_in / o.eps_out, vk, z_.p);
-        op(z_.p, w_.p);
-      }
+      op(z_.p, w_.p);
       // CGS2
       launch_mdot(s_, n, k + 1, V_.p, ld, w_.p, partial_.p, hbuf_.p);
       launch_gemv_sub(s_, n, k + 1, V_.p, ld, hbuf_.p, w_.p);
@@ -623,11 +649,15 @@ int Runtime::gmres(const double *b, double *x, bool transpose, int *iters) {
     PBMP_HIP(hipMemcpyAsync(ybuf_.p, y.data(), sizeof(double) * k_done,
                             hipMemcpyHostToDevice, s_));
     if (transpose) {
-      // x += V y (unpreconditioned)
-      for (int i = 0; i < k_done; ++i) {
-        // small k_done: axpy per basis vector, coefficients from the host
-        launch_axpy(s_, n, y[i], V_.p + (size_t)i * ld, x);
-      }
+      // x += M^{-T} (V y)
+      for (int i = 0; i < k_done; ++i) y[i] = -y[i];
+      PBMP_HIP(hipMemcpyAsync(ybuf_.p, y.data(), sizeof(double) * k_done,
+                              hipMemcpyHostToDevice, s_));
+      PBMP_HIP(hipMemsetAsync(ax_.p, 0, sizeof(double) * n, s_));
+      launch_gemv_sub(s_, n, k_done, V_.p, ld, ybuf_.p, ax_.p);
+      precond_T(ax_.p, z_.p);
+      launch_axpy(s_, n, 1.0, z_.p, x);
+      sync();
     } else {
       launch_update_solution(s_, N, k_done, V_.p, ld, ybuf_.p, diag_.p,
                              o.eps_in / o.eps_out, x);

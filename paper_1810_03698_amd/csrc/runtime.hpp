@@ -81,12 +81,13 @@ class Runtime {
   Dbuf<int> trow_, tcol_;  // transposed near structure (entry ids)
   Dbuf<int> tent_;
   bool tree_active_ = false;
+  bool floor_r2_ = true;  // FP32 distance floor needed (tiny panels present)
   std::unique_ptr<Tree> tree_;
 
   // ---- sites ----
   int M_ = 0;
   Dbuf<double> sxyz_, sq_, sd_, sQ_, salpha_;
-  Dbuf<int> sgroup_, srow_, scol_;
+  Dbuf<int> sgroup_, srow_, scol_, tsrow_, tscol_;
   std::vector<double> h_sxyz_;
 
   // ---- work ----
@@ -109,6 +110,7 @@ class Runtime {
   // y = A x (internal order, device)
   void apply(const double *x, double *y);
   void apply_transpose(const double *x, double *y);
+  void precond_T(const double *u, double *z);
   // GMRES on A x = b (device, internal order), x holds the initial guess.
   int gmres(const double *b, double *x, bool transpose, int *iters);
   // readout at the sites for surface solution x (internal): out [M*nout]

@@ -18,8 +18,8 @@
 namespace pbmp {
 
 namespace {
-constexpr int kP2PChunkPanels = 1536;  // source panels per P2P task
-constexpr int kM2PChunkBoxes = 32;     // boxes per M2P task
+constexpr int kP2PChunkPanels = 512;   // source panels per P2P task
+constexpr int kM2PChunkBoxes = 16;     // boxes per M2P task
 }  // namespace
 
 void Tree::build(int N, const double *cen, int nf,
