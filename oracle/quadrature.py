@@ -11,8 +11,9 @@ fully symmetric degree-9 rule with orbit structure
   1 centroid + 4 orbits (a, a, 1-2a) + 1 orbit (a, b, 1-a-b)   (19 nodes),
 whose 12 unknowns are fixed by exactness on every monomial of degree <= 9.
 It is obtained here by solving those moment equations (nonlinear least
-squares from a rough start), and accepted only if all weights are positive,
-all nodes interior and every moment is exact to ~1e-15.
+squares from a rough start, then Gauss-Newton at 40 significant digits),
+and accepted only if all weights are positive, all nodes interior and
+every moment is exact to 1e-30 before rounding to double.
 
 Weights are normalised to sum to 1 (multiply by the panel area).
 """
@@ -68,6 +69,57 @@ def _residual19(t, deg=9):
 _RULE19 = None
 
 
+def _refine19(t, digits=40, iters=6):
+    """Gauss-Newton on the moment equations in mpmath arithmetic.  The
+    system is ill-conditioned (a double-precision solution with residual
+    ~1e-16 can sit ~1e-11 away from the rule), so the rule is refined at
+    `digits` decimal digits and each barycentric coordinate and weight is
+    rounded to double once, at the end."""
+    import mpmath as mp
+    with mp.workdps(digits):
+        def nodes(t):
+            third = mp.mpf(1) / 3
+            pts, wts = [(third, third)], [t[0]]
+            for k in range(4):
+                a, w = t[1 + 2 * k], t[2 + 2 * k]
+                for p in ((a, 1 - 2 * a), (1 - 2 * a, a), (a, a)):
+                    pts.append(p)
+                    wts.append(w)
+            a, b, w = t[9], t[10], t[11]
+            c = 1 - a - b
+            for p in ((b, c), (c, b), (a, c), (c, a), (a, b), (b, a)):
+                pts.append(p)
+                wts.append(w)
+            return pts, wts
+
+        def residual(t):
+            pts, wts = nodes(t)
+            r = []
+            for i in range(10):
+                for j in range(10 - i):
+                    ex = 2 * mp.factorial(i) * mp.factorial(j) / mp.factorial(i + j + 2)
+                    r.append(mp.fsum(w * x ** i * y ** j for w, (x, y) in zip(wts, pts)) - ex)
+            return mp.matrix(r)
+
+        t = mp.matrix([mp.mpf(float(v)) for v in t])
+        h = mp.mpf(10) ** (-(digits * 2) // 3)
+        for _ in range(iters):
+            r = residual(t)
+            J = mp.matrix(len(r), 12)
+            for k in range(12):
+                tp = t.copy()
+                tp[k] += h
+                rp = residual(tp)
+                for i in range(len(r)):
+                    J[i, k] = (rp[i] - r[i]) / h
+            t = t + mp.lu_solve(J.T * J, -(J.T * r))
+        res = max(abs(v) for v in residual(t))
+        pts, wts = nodes(t)
+        bary = np.array([[float(1 - x - y), float(x), float(y)] for x, y in pts])
+        w = np.array([float(v) for v in wts])
+        return bary, w, float(res)
+
+
 def tri19():
     """Barycentric nodes [19,3] and weights [19] of the degree-9 rule."""
     global _RULE19
@@ -76,10 +128,8 @@ def tri19():
                        0.025, 0.037, 0.22, 0.043])
         sol = least_squares(_residual19, t0, xtol=1e-15, ftol=1e-15,
                             gtol=1e-15, method="lm")
-        t = sol.x
-        bary, w = _expand19(t)
-        res = np.abs(_residual19(t)).max()
-        if not (res < 1e-14 and (w > 0).all() and (bary > 0).all()):
+        bary, w, res = _refine19(sol.x)
+        if not (res < 1e-30 and (w > 0).all() and (bary > 0).all()):
             raise RuntimeError("19-point rule did not converge (res=%g)" % res)
         _RULE19 = (bary, w)
     return _RULE19

@@ -46,6 +46,27 @@ def test_nineteen_point_rule_degree_nine():
     assert max(_moment_err(b, w, i, 10 - i) for i in range(11)) > 1e-9
 
 
+
+def test_nineteen_point_rule_published_values():
+    """The rule equals the published symmetric degree-9, 19-point rule
+    (D. A. Dunavant, Int. J. Numer. Meth. Eng. 21 (1985) 1129, table for
+    degree 9; weights normalised to sum 1, values printed to 15 digits)."""
+    b, w = quadrature.tri19()
+    printed = [  # (weight, barycentric node of one orbit member)
+        (0.097135796282799, (1 / 3, 1 / 3, 1 / 3)),
+        (0.031334700227139, (0.020634961602525, 0.489682519198738, 0.489682519198738)),
+        (0.077827541004774, (0.125820817014127, 0.437089591492937, 0.437089591492937)),
+        (0.079647738927210, (0.623592928761935, 0.188203535619033, 0.188203535619033)),
+        (0.025577675658698, (0.910540973211095, 0.044729513394453, 0.044729513394453)),
+        (0.043283539377289, (0.036838412054736, 0.221962989160766, 0.741198598784498)),
+    ]
+    for wt, node in printed:
+        d = np.abs(np.sort(b, axis=1) - np.sort(node)).max(axis=1)
+        q = np.argmin(d)
+        assert d[q] < 1e-14 and abs(w[q] - wt) < 1e-14
+    # orbit multiplicities 1 + 3 + 3 + 3 + 3 + 6
+    assert sorted(np.unique(np.round(w, 12), return_counts=True)[1]) == [1, 3, 3, 3, 3, 6]
+
 # ---------------------------------------------------------- singular panels
 def _adaptive_panel_integral(v, c, kernel):
     """int over triangle v of kernel(|c - y|) dy, by splitting at c into
