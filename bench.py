@@ -28,9 +28,19 @@ PEAK_FP32_NONPACKED = 78.6  # 256 CU x 64 lanes x 2 FLOP x 2.4 GHz
 
 
 def _m2p_flops(order):
-    """FLOP per (target, box) pair of the Taylor evaluation."""
-    ncoef = (order + 1) * (order + 2) * (order + 3) // 6
-    return 40 * ncoef
+    """FLOP per (target, box) pair of the implemented M2P evaluation: per
+    coefficient k != 0 of the Laplace/Yukawa recurrences 6 n1 + 3 n2 + 13
+    (n1, n2 = number of k_i >= 1, >= 2), 8 for the four moment dot products
+    per coefficient, and 14 for the pair set-up (FMA = 2)."""
+    total = 14
+    for s in range(order + 1):
+        for i in range(s, -1, -1):
+            for j in range(s - i, -1, -1):
+                k = (i, j, s - i - j)
+                total += 8
+                if s:
+                    total += 6 * sum(e >= 1 for e in k) + 3 * sum(e >= 2 for e in k) + 13
+    return total
 
 
 def cpu_baseline(w, target_seconds):
@@ -140,7 +150,13 @@ def main():
                 "traffic": None, "kernel": name, "avg_launch_ms": avg_ms,
                 "frac_of_nonpacked_fp32": achieved / PEAK_FP32_NONPACKED,
                 "p2p_ms_total": st["p2p_ms"], "m2p_ms_total": st["m2p_ms"],
-                "p2m_ms_total": st["p2m_ms"]}
+                "p2m_ms_total": st["p2m_ms"],
+                "p2p_avg_ms": p2p_avg, "m2p_avg_ms": m2p_avg,
+                "p2p_pairs_per_launch": st["p2p_pairs"] / max(1, st["p2p_launches"]),
+                "m2p_pairs_per_launch": st["m2p_pairs"] / max(1, st["m2p_launches"]),
+                "p2p_tflops_alg": ALG_FLOP_PER_PAIR * st["p2p_pairs"] / max(1e-30, st["p2p_ms"]) / 1e9,
+                "m2p_tflops_alg": _m2p_flops(int(p.get("order_P", 4))) * st["m2p_pairs"]
+                / max(1e-30, st["m2p_ms"]) / 1e9}
 
     solve_cmp = None
     if args.fp64_steps > 0:

@@ -173,11 +173,18 @@ int pbmp_site_fields(pbmp_ctx *c, const double *x, double *out, int where);
 
 /* Gradient of dG_bar * dG with respect to site positions g_xyz [3m],
  * charges g_q [m], dipoles g_d [3m], quadrupole entries g_Q9 [9m] (the nine
- * entries taken as independent) and vertex positions g_verts [3nv], by the
- * adjoint of the converged solve (transposed operator, transposed
- * induced-dipole loop).  Needs a successful pbmp_solve with unchanged
- * inputs (PBMP_ESTATE otherwise).  Any output may be NULL (skipped).
- * Direct mode only for g_verts (PBMP_EARG in treecode mode). */
+ * entries taken as independent, as they enter eq. rhs_multipole and eq.
+ * energy_multipole_polarizable) and vertex positions g_verts [3nv], by the
+ * adjoint of the converged solve: relaxed transposed induced-dipole loops,
+ * GMRES on the transposed operator, and the explicit derivatives of every
+ * pair term (operator entries including near-singular and singular panels,
+ * right-hand side, readout, Coulomb and Thole interactions).  Near/far
+ * decisions and lists are held fixed.  Needs a successful pbmp_solve with
+ * unchanged inputs (PBMP_ESTATE otherwise).  Any output may be NULL
+ * (skipped).  In treecode mode the adjoint products are direct (O(nt^2)), so
+ * the gradient is that of the direct-operator energy at the treecode
+ * solution (agreement to the treecode's accuracy).  Returns +1/+2 when an
+ * adjoint solve did not converge. */
 int pbmp_backward(pbmp_ctx *c, double dG_bar, double *g_xyz, double *g_q,
                   double *g_d, double *g_Q9, double *g_verts, int where);
 

@@ -9,4 +9,11 @@ solve/backward as a ``torch.autograd.Function``.
 from . import pbmp
 from .pbmp import Solver, load, PbmpError
 
-__all__ = ["pbmp", "Solver", "load", "PbmpError"]
+
+def solvation_energy(*args, **kwargs):
+    """Differentiable solvation energy (see autograd.solvation_energy)."""
+    from .autograd import solvation_energy as f
+    return f(*args, **kwargs)
+
+
+__all__ = ["pbmp", "Solver", "load", "PbmpError", "solvation_energy"]

@@ -50,6 +50,14 @@ void launch_scale_sites(hipStream_t s, int M, const double *alpha, const double 
                         double *w);
 void launch_adj_update(hipStream_t s, int M, double omega, const double *E, const double *F,
                        const double *J, double Jsign, double *lam, double *out2);
+void launch_mesh_adjoint(hipStream_t s, int N, int M, int nf, const double *src64,
+                         const double *geo, const double *verts, const int *tri,
+                         const RuleArgs &ru, const int *rowptr, const int *col,
+                         const int *trow, const int *tent, const int *tsrow,
+                         const int *tscol, const double *x, const double *lam,
+                         const double *sigma, const double *xyz, const double *q,
+                         const double *p, const double *Q, const double *Wp, double kappa,
+                         double eps_ratio, double *work, double *ge, double *out);
 
 void Runtime::apply_transpose(const double *x, double *y) {
   launch_transpose(s_, fp64(), ru_.nf, N_, src64_.p, src32_.p, geo_.p, tgt32_.p, x, o.kappa,
@@ -66,8 +74,6 @@ int Runtime::backward(double dGbar, double *g_xyz, double *g_q, double *g_d, dou
                       double *g_verts, int where) {
   PBMP_REQUIRE(solved_, PBMP_ESTATE, "backward needs a completed solve on this context");
   PBMP_REQUIRE(where == PBMP_HOST || where == PBMP_DEVICE, PBMP_EARG, "bad where");
-  PBMP_REQUIRE(g_verts == nullptr, PBMP_EARG,
-               "vertex gradients are not available in this build (pass NULL)");
   const int M = M_, N = N_;
   const double c = dGbar * coulomb_kcal() * 0.5;
   const double ta = o.thole_a, eps = o.eps_in;
@@ -169,6 +175,27 @@ int Runtime::backward(double dGbar, double *g_xyz, double *g_q, double *g_d, dou
         oQ[9 * l + 3 * x + y] = c * (r[up[x][y]] + in[up[x][y]]) / 6.0 + Q1[9 * l + 3 * x + y] +
                                 Q3[9 * l + 3 * x + y];
   }
+  std::vector<double> overts;
+  if (g_verts) {
+    // mesh: operator entries, right-hand side at the collocation points and
+    // the readout, chained to the vertices
+    Dbuf<double> work, ge, pv;
+    work.alloc(25 * (size_t)N);
+    ge.alloc(12 * (size_t)std::max(nnz_, 1));
+    pv.alloc(9 * (size_t)N);
+    launch_mesh_adjoint(s_, N, M, ru_.nf, src64_.p, geo_.p, verts_.p, tri_.p, ru_, nrow_.p,
+                        ncol_.p, trow_.p, tent_.p, tsrow_.p, tscol_.p, x_.p, lx.p, sig.p,
+                        sxyz_.p, sq_.p, p_.p, sQ_.p, Wp.p, o.kappa, o.eps_in / o.eps_out,
+                        work.p, ge.p, pv.p);
+    std::vector<double> hp(9 * (size_t)N);
+    pv.download(hp.data(), hp.size(), s_);
+    sync();
+    overts.assign(3 * (size_t)Nv_, 0.0);
+    for (int j = 0; j < N; ++j)
+      for (int a = 0; a < 3; ++a)
+        for (int d = 0; d < 3; ++d)
+          overts[3 * (size_t)h_tri_[3 * (size_t)j + a] + d] += hp[9 * (size_t)j + 3 * a + d];
+  }
   auto put = [&](double *dst, const std::vector<double> &src) {
     if (!dst) return;
     PBMP_HIP(hipMemcpyAsync(dst, src.data(), sizeof(double) * src.size(),
@@ -179,6 +206,7 @@ int Runtime::backward(double dGbar, double *g_xyz, double *g_q, double *g_d, dou
   put(g_q, oq);
   put(g_d, od);
   put(g_Q, oQ);
+  put(g_verts, overts);
   sync();
   return warn;
 }

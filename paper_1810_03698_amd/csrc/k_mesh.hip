@@ -5,6 +5,7 @@
 
 #include "kernels.hpp"
 #include "pair.hpp"
+#include "panel.hpp"
 
 namespace pbmp {
 
@@ -68,79 +69,6 @@ __global__ void k_panel_geometry(int N, const double *__restrict__ verts,
   }
 }
 
-// V_L and V_Y of a flat panel seen from a point c lying inside it.  The
-// panel is split at c into three sub-triangles; for edge (a, b) at distance h
-// from c, with s the signed coordinate along the edge from the foot of the
-// perpendicular, the radial integral is done in closed form:
-//   int 1/(4 pi r) dA         = 1/(4 pi) h [asinh(s_b/h) - asinh(s_a/h)],
-//   int e^{-k r}/(4 pi r) dA  = 1/(4 pi) int (1 - e^{-k rho})/k dtheta,
-// rho = h / cos(theta) the distance to the edge.  The Yukawa remainder
-// (1 - e^{-k rho})/k - rho is integrated over u = asinh(s/h) (rho = h cosh u,
-// dtheta = du / cosh u) with Gauss-Legendre nodes along the edge.
-__device__ void singular_panel(const double v[3][3], const double c[3],
-                               double kappa, const RuleArgs &ru, double &VL,
-                               double &VY) {
-  double lap = 0.0, rem = 0.0;
-  for (int e = 0; e < 3; ++e) {
-    const double *a = v[e];
-    const double *b = v[e == 2 ? 0 : e + 1];
-    const double ab[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
-    const double len = sqrt(ab[0] * ab[0] + ab[1] * ab[1] + ab[2] * ab[2]);
-    const double t[3] = {ab[0] / len, ab[1] / len, ab[2] / len};
-    const double ca[3] = {a[0] - c[0], a[1] - c[1], a[2] - c[2]};
-    const double sa = ca[0] * t[0] + ca[1] * t[1] + ca[2] * t[2];
-    const double sb = sa + len;
-    // h = |ca x t|
-    const double x0 = ca[1] * t[2] - ca[2] * t[1];
-    const double x1 = ca[2] * t[0] - ca[0] * t[2];
-    const double x2 = ca[0] * t[1] - ca[1] * t[0];
-    const double h = sqrt(x0 * x0 + x1 * x1 + x2 * x2);
-    const double ua = asinh(sa / h), ub = asinh(sb / h);
-    lap += h * (ub - ua);
-    if (kappa > 0.0) {
-      const double half = 0.5 * (ub - ua), mid = 0.5 * (ub + ua);
-      double acc = 0.0;
-      for (int g = 0; g < ru.ngl; ++g) {
-        const double u = mid + half * ru.glx[g];
-        const double ch = cosh(u);
-        const double rho = h * ch;
-        acc += ru.glw[g] * (-expm1(-kappa * rho) / kappa - rho) / ch;
-      }
-      rem += half * acc;
-    }
-  }
-  VL = lap * kInv4Pi;
-  VY = (lap + rem) * kInv4Pi;
-}
-
-// (V_L, K_L, V_Y, K_Y) of panel v (normal n, area A) at point x with the
-// nq-node rule (b, w).
-__device__ void panel_rule(const double v[3][3], const double n[3], double A,
-                           const double x[3], int nq, const double (*b)[3],
-                           const double *w, double kappa, double out[4]) {
-  double vl = 0.0, kl = 0.0, vy = 0.0, ky = 0.0;
-  for (int q = 0; q < nq; ++q) {
-    double R[3];
-    for (int d = 0; d < 3; ++d)
-      R[d] = x[d] - (b[q][0] * v[0][d] + b[q][1] * v[1][d] + b[q][2] * v[2][d]);
-    const double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
-    const double r = sqrt(r2);
-    const double inv = 1.0 / r;
-    const double inv3 = inv / r2;
-    const double nR = n[0] * R[0] + n[1] * R[1] + n[2] * R[2];
-    const double ek = exp(-kappa * r);
-    const double wA = w[q] * A;
-    vl += wA * inv;
-    kl += wA * nR * inv3;
-    vy += wA * ek * inv;
-    ky += wA * nR * (1.0 + kappa * r) * ek * inv3;
-  }
-  out[0] = vl * kInv4Pi;
-  out[1] = kl * kInv4Pi;
-  out[2] = vy * kInv4Pi;
-  out[3] = ky * kInv4Pi;
-}
-
 __global__ void k_near_values(int fp64, int N, const int *__restrict__ rowptr,
                               const int *__restrict__ col,
                               const double *__restrict__ verts,
@@ -162,13 +90,13 @@ __global__ void k_near_values(int fp64, int N, const int *__restrict__ rowptr,
     const double A = geo[6 * N + j];
     double fine[4], coarse[4];
     if (j == i) {
-      singular_panel(v, x, kappa, ru, fine[0], fine[2]);
+      singular_panel_t<double>(v, x, kappa, ru, fine[0], fine[2]);
       fine[1] = 0.0;
       fine[3] = 0.0;
       diag[i] = fine[0];
       diag[N + i] = fine[2];
     } else {
-      panel_rule(v, n, A, x, ru.nn, ru.nb, ru.nw, kappa, fine);
+      panel_rule_t<double>(v, n, A, x, ru.nn, ru.nb, ru.nw, kappa, fine);
     }
     // the far-rule value exactly as the far-field product evaluates it
     const double wA = A * kInv4Pi / ru.nf;

@@ -387,6 +387,7 @@ void Runtime::build_near_lists() {
   }
   nrow_.upload(row.data(), row.size(), s_);
   ncol_.upload(col.data(), col.size(), s_);
+  nnz_ = (int)col.size();
   nval_.alloc(4 * col.size());
   diag_.alloc(2 * (size_t)N);
   launch_near_values(s_, fp64(), N, nrow_.p, ncol_.p, verts_.p, tri_.p, geo_.p,

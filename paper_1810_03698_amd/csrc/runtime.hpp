@@ -77,6 +77,7 @@ class Runtime {
   std::vector<double> h_verts_;
   std::vector<int> h_tri_;  // internal order
   Dbuf<int> nrow_, ncol_;
+  int nnz_ = 0;
   Dbuf<double> nval_, diag_;
   Dbuf<int> trow_, tcol_;  // transposed near structure (entry ids)
   Dbuf<int> tent_;

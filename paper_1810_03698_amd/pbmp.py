@@ -252,15 +252,27 @@ class Solver:
                                               _common_where([a, o])))
         return out
 
-    def backward(self, dG_bar=1.0, verts=True):
-        g = dict(xyz=np.empty((self.m, 3)), q=np.empty(self.m),
-                 d=np.empty((self.m, 3)), Q9=np.empty((self.m, 9)))
+    def backward(self, dG_bar=1.0, verts=True, device=None):
+        """Gradients of dG_bar * dG (see pbmp_backward).  Host numpy arrays by
+        default; torch tensors on `device` when given (written by the library
+        directly into device memory)."""
+        shapes = dict(xyz=(self.m, 3), q=(self.m,), d=(self.m, 3), Q9=(self.m, 9))
         if verts:
-            g["verts"] = np.empty((self.nv, 3))
-        ptr = lambda k: g[k].ctypes.data if k in g else None
-        self._check(self.lib.pbmp_backward(self.ctx, float(dG_bar), ptr("xyz"),
-                                           ptr("q"), ptr("d"), ptr("Q9"),
-                                           ptr("verts"), HOST))
+            shapes["verts"] = (self.nv, 3)
+        if device is None:
+            g = {k: np.empty(v) for k, v in shapes.items()}
+            ptr = lambda k: g[k].ctypes.data if k in g else None
+            where = HOST
+        else:
+            import torch
+            g = {k: torch.empty(v, dtype=torch.float64, device=device)
+                 for k, v in shapes.items()}
+            ptr = lambda k: g[k].data_ptr() if k in g else None
+            where = DEVICE
+        rc = self._check(self.lib.pbmp_backward(self.ctx, float(dG_bar), ptr("xyz"),
+                                                ptr("q"), ptr("d"), ptr("Q9"),
+                                                ptr("verts"), where), allow_warn=True)
+        g["status"] = rc
         return g
 
     def kernel_stats(self, enable=None):

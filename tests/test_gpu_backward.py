@@ -151,3 +151,74 @@ def test_backward_ragged_positions_fd():
     err = np.abs(got - fd).max() / np.abs(fd).max()
     print("ragged", err)
     assert err < 1e-4
+
+
+def _gpu_grad_verts(w, precision="fp64"):
+    from paper_1810_03698_amd import Solver
+    s = Solver(mode="direct", precision=precision, gmres_tol=1e-13,
+               scf_tol_debye=1e-12, scf_maxit=500)
+    s.set_mesh(w["verts"], w["tris"])
+    s.set_sites(w["xyz"], w["q"], w["d"], w["Q9"], w["alpha"])
+    s.solve(outputs=False)
+    return s.backward(1.0, verts=True)
+
+
+@pytest.fixture(scope="module")
+def cfg0_grad_verts(cfg0):
+    return _gpu_grad_verts(cfg0)
+
+
+def test_backward_vertices_vs_oracle_fd(cfg0, cfg0_grad_verts):
+    """Vertex moves of 1e-5 A keep every near/far decision (smallest margin
+    to the threshold on this mesh: 0.025 A)."""
+    g = cfg0_grad_verts
+    rng = np.random.default_rng(9)
+    vids = rng.choice(len(cfg0["verts"]), 4, replace=False)
+    h = 1e-5
+    got, fd = [], []
+    for v in vids:
+        for k in range(3):
+            vals = []
+            for sgn in (1.0, -1.0):
+                vv = cfg0["verts"].copy()
+                vv[v, k] += sgn * h
+                sol = osolver.BemSolvent(vv, cfg0["tris"], 1.0, 80.0, 0.125)
+                vals.append(osolver.solvation(cfg0["xyz"], cfg0["q"], cfg0["d"],
+                                              cfg0["Q9"], cfg0["alpha"], sol,
+                                              tol_debye=1e-12, maxit=2000)["dG"])
+            fd.append((vals[0] - vals[1]) / (2 * h))
+            got.append(g["verts"][v, k])
+    got, fd = np.array(got), np.array(fd)
+    err = np.abs(got - fd).max() / np.abs(fd).max()
+    print("verts", err, np.c_[got, fd][:6])
+    assert err < 1e-4
+
+
+def test_backward_rigid_translation_invariance(cfg0_grad_verts):
+    """Moving every site and every vertex by the same vector changes
+    nothing: the site and vertex gradients sum to zero."""
+    g = cfg0_grad_verts
+    tot = g["xyz"].sum(0) + g["verts"].sum(0)
+    scale = np.abs(g["xyz"]).sum() + np.abs(g["verts"]).sum()
+    print(tot, scale)
+    assert np.abs(tot).max() < 1e-9 * scale
+
+
+def test_autograd_function_matches_backward(cfg0, cfg0_grad_verts):
+    import torch
+    from paper_1810_03698_amd import solvation_energy
+    dev = torch.device("cuda:0")
+    t = lambda a, req=False: torch.tensor(a, dtype=torch.float64, device=dev,
+                                          requires_grad=req)
+    verts, xyz, q, d, Q9 = (t(cfg0[k], True) for k in ("verts", "xyz", "q", "d", "Q9"))
+    tris = torch.tensor(cfg0["tris"], dtype=torch.int32, device=dev)
+    alpha = t(cfg0["alpha"])
+    dG = solvation_energy(verts, tris, xyz, q, d, Q9, alpha, mode="direct",
+                          precision="fp64", gmres_tol=1e-13, scf_tol_debye=1e-12,
+                          scf_maxit=500)
+    (2.0 * dG).backward()
+    g = cfg0_grad_verts
+    for name, tens in (("xyz", xyz), ("q", q), ("d", d), ("Q9", Q9), ("verts", verts)):
+        ref = 2.0 * g[name].reshape(tens.shape)
+        got = tens.grad.cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-9 * np.abs(ref).max(), name
