@@ -22,6 +22,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+COPY_BYTES = 256 << 20
 ALG_FLOP_PER_PAIR = 33  # four kernels per (target, far-field node) pair
 PEAK_FP32_VECTOR = 157.3  # TFLOP/s, MI355X published (packed FP32)
 PEAK_FP32_NONPACKED = 78.6  # 256 CU x 64 lanes x 2 FLOP x 2.4 GHz
@@ -82,6 +83,9 @@ def main():
                     help="FP64 solves timed for the mixed-vs-FP64 comparison (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 256 MiB device-to-device copy first (the reference "
+                         "dispatch for scaling FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -115,6 +119,13 @@ def main():
         s.set_mesh(t(w["verts"]), t(w["tris"], torch.int32))
         s.set_sites(t(w["xyz"]), t(w["q"]), t(w["d"]), t(w["Q9"]), t(w["alpha"]))
         return s
+
+    if args.copy_calibration:
+        a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     N = len(w["tris"])
     G = int(p["gauss_far"]) * N

@@ -17,7 +17,6 @@ namespace pbmp {
 
 namespace {
 
-constexpr double kInv4Pi = 0.07957747154594767;
 using D3 = Dual<3>;
 
 // ---- pair functions, templated on the scalar type -----------------------

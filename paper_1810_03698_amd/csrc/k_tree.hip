@@ -25,7 +25,6 @@ namespace pbmp {
 
 namespace {
 
-constexpr double kInv4Pi = 0.07957747154594767;
 
 // Multi-indices |k| <= P ordered by degree, then x exponent descending,
 // then y exponent descending; m1/m2: positions of k - e_i and k - 2 e_i.
@@ -61,6 +60,12 @@ template <int P> struct Multi {
         }
   }
 };
+
+// binomial coefficients C(a, b), a, b <= 6
+__constant__ double kBinom[7][7] = {
+    {1, 0, 0, 0, 0, 0, 0},   {1, 1, 0, 0, 0, 0, 0},    {1, 2, 1, 0, 0, 0, 0},
+    {1, 3, 3, 1, 0, 0, 0},   {1, 4, 6, 4, 1, 0, 0},    {1, 5, 10, 10, 5, 1, 0},
+    {1, 6, 15, 20, 15, 6, 1}};
 
 inline int ncoef_of(int P) { return (P + 1) * (P + 2) * (P + 3) / 6; }
 
@@ -136,7 +141,9 @@ __global__ __launch_bounds__(256) void k_p2m(int nf, const int *__restrict__ lea
 
 // ---------------------------------------------------------------- M2M
 // (h + t)^k = sum_{j <= k} C(k, j) t^{k-j} h^j, t = child centre - parent
-// centre; one block per parent box, one lane per coefficient.
+// centre; one block per parent box, one lane per coefficient.  The
+// children's moments are staged in LDS first (one coalesced read), so the
+// shift itself runs at LDS latency.
 template <int P>
 __global__ __launch_bounds__(64) void k_m2m(const int *__restrict__ boxes,
                                             const int *__restrict__ child,
@@ -145,41 +152,43 @@ __global__ __launch_bounds__(64) void k_m2m(const int *__restrict__ boxes,
   constexpr Multi<P> mi{};
   constexpr int NC = Multi<P>::n;
   __shared__ double tp[8][3][P + 1];
-  __shared__ double binom[P + 1][P + 1];
+  __shared__ double cm[8][2 * NC];
+  __shared__ int cid[8];
   const int B = boxes[blockIdx.x];
-  if (threadIdx.x == 0) {
-    for (int a = 0; a <= P; ++a) {
-      binom[a][0] = 1.0;
-      for (int b = 1; b <= P; ++b) binom[a][b] = (b > a) ? 0.0 : binom[a][b - 1] * (a - b + 1) / b;
-    }
-  }
+  if (threadIdx.x < 8) cid[threadIdx.x] = child[8 * B + threadIdx.x];
+  __syncthreads();
   int nch = 0;
-  for (int cc = 0; cc < 8; ++cc) nch += child[8 * B + cc] >= 0;
+  for (int cc = 0; cc < 8; ++cc) nch += cid[cc] >= 0;
   if (threadIdx.x < 3 * nch) {
     const int cc = threadIdx.x / 3, d = threadIdx.x % 3;
-    const int C = child[8 * B + cc];
-    const double t = center[3 * C + d] - center[3 * B + d];
+    const double t = center[3 * cid[cc] + d] - center[3 * B + d];
     double p = 1.0;
     for (int e = 0; e <= P; ++e) {
       tp[cc][d][e] = p;
       p *= t;
     }
   }
+  for (int e = threadIdx.x; e < nch * 2 * NC; e += 64) {
+    const int cc = e / (2 * NC), k = e % (2 * NC);
+    cm[cc][k] = mom[(size_t)cid[cc] * 2 * NC + k];
+  }
   __syncthreads();
   for (int k = threadIdx.x; k < NC; k += 64) {
     const int kx = mi.e[k][0], ky = mi.e[k][1], kz = mi.e[k][2];
     double m = 0.0, mkk = 0.0;
     for (int cc = 0; cc < nch; ++cc) {
-      const double *cm = mom + (size_t)child[8 * B + cc] * 2 * NC;
-      for (int jx = 0; jx <= kx; ++jx)
-        for (int jy = 0; jy <= ky; ++jy)
+      for (int jx = 0; jx <= kx; ++jx) {
+        const double wx = kBinom[kx][jx] * tp[cc][0][kx - jx];
+        for (int jy = 0; jy <= ky; ++jy) {
+          const double wxy = wx * kBinom[ky][jy] * tp[cc][1][ky - jy];
           for (int jz = 0; jz <= kz; ++jz) {
             const int jd = Multi<P>::index(jx, jy, jz);
-            const double w = binom[kx][jx] * binom[ky][jy] * binom[kz][jz] *
-                             tp[cc][0][kx - jx] * tp[cc][1][ky - jy] * tp[cc][2][kz - jz];
-            m += w * cm[jd];
-            mkk += w * cm[NC + jd];
+            const double w = wxy * kBinom[kz][jz] * tp[cc][2][kz - jz];
+            m += w * cm[cc][jd];
+            mkk += w * cm[cc][NC + jd];
           }
+        }
+      }
     }
     mom[(size_t)B * 2 * NC + k] = m;
     mom[(size_t)B * 2 * NC + NC + k] = mkk;
@@ -192,21 +201,51 @@ __global__ void k_cast(size_t n, const double *__restrict__ a, float *__restrict
 }
 
 // ------------------------------------------------------------ P2P tasks
-// One 64-lane block per task: targets [t0, t1) of a leaf (TPT per lane),
-// sources = panels of the listed leaves, streamed through LDS.
+// One 64-lane block per task: targets [t0, t1) of a leaf, sources = the
+// task's panel sub-ranges, streamed through LDS.  Leaves are often much
+// smaller than a wave, so the lanes are split into G groups of L = 64 / G:
+// every group holds all targets (TPT per lane) and takes every G-th source
+// panel of a tile; the groups' FP64 sums are added in LDS in a fixed order.
+// G and TPT are chosen per task to use the most lanes.
 constexpr int kTileT = 128;
+constexpr int kMaxTPT = 5;
+
+struct LaneSplit {
+  int G, L, tpt;
+};
+
+// G, L = 64 / G and targets per lane for nt targets: maximise the useful
+// fraction G nt / (64 tpt) with tpt <= kMaxTPT (ties: fewer groups)
+__device__ inline LaneSplit lane_split(int nt) {
+  LaneSplit best{1, 64, min(kMaxTPT, (nt + 63) / 64)};
+  float be = (float)nt / (64.0f * best.tpt * ((nt + 64 * best.tpt - 1) / (64 * best.tpt)));
+  for (int G = 2; G <= 16; ++G) {
+    const int L = 64 / G;
+    const int tpt = (nt + L - 1) / L;
+    if (tpt > kMaxTPT) continue;
+    const float e = (float)(G * nt) / (64.0f * tpt);
+    if (e > be) {
+      be = e;
+      best = LaneSplit{G, L, tpt};
+    }
+  }
+  return best;
+}
 
 template <class T, int NF, int TPT, bool FLOOR>
 __device__ void p2p_task_body(const T *__restrict__ src, const T *__restrict__ tgt,
                               int N, int t0, int t1, const int *__restrict__ ranges,
                               int lb, int le, T kappa, T nk, int slot,
-                              double *__restrict__ part, T *sh) {
-  for (int tb = t0; tb < t1; tb += 64 * TPT) {
+                              double *__restrict__ part, T *sh, double *red, int G, int L) {
+  const int lane = (int)threadIdx.x;
+  const int gi = lane / L, li = lane - gi * L;
+  const bool active = gi < G;
+  for (int tb = t0; tb < t1; tb += L * TPT) {
     T px[TPT], py[TPT], pz[TPT];
     int ti[TPT];
 #pragma unroll
     for (int k = 0; k < TPT; ++k) {
-      ti[k] = tb + k * 64 + (int)threadIdx.x;
+      ti[k] = tb + k * L + li;
       const int tl = min(ti[k], t1 - 1);
       px[k] = tgt[tl];
       py[k] = tgt[N + tl];
@@ -221,13 +260,13 @@ __device__ void p2p_task_body(const T *__restrict__ src, const T *__restrict__ t
       for (int jt = s0; jt < s1; jt += kTileT) {
         const int nj = min(kTileT, s1 - jt);
         __syncthreads();
-        for (int e = threadIdx.x; e < nj * 16; e += 64) sh[e] = src[(size_t)jt * 16 + e];
+        for (int e = lane; e < nj * 16; e += 64) sh[e] = src[(size_t)jt * 16 + e];
         __syncthreads();
         T a[TPT][4];
 #pragma unroll
         for (int k = 0; k < TPT; ++k)
           for (int c = 0; c < 4; ++c) a[k][c] = T(0);
-        for (int jj = 0; jj < nj; ++jj) {
+        for (int jj = active ? gi : nj; jj < nj; jj += G) {
           const T *r = sh + 16 * jj;
 #pragma unroll
           for (int k = 0; k < TPT; ++k) {
@@ -271,10 +310,25 @@ __device__ void p2p_task_body(const T *__restrict__ src, const T *__restrict__ t
           for (int c = 0; c < 4; ++c) S[k][c] += (double)a[k][c];
       }
     }
+    if (G > 1) {
+      // groups 1..G-1 hand their sums to group 0 through LDS
+      __syncthreads();
+      if (active && gi > 0)
 #pragma unroll
-    for (int k = 0; k < TPT; ++k)
-      if (ti[k] < t1)
-        for (int c = 0; c < 4; ++c) part[((size_t)slot * 4 + c) * N + ti[k]] = S[k][c];
+        for (int k = 0; k < TPT; ++k)
+          for (int c = 0; c < 4; ++c) red[((gi - 1) * L + li) * (4 * TPT) + 4 * k + c] = S[k][c];
+      __syncthreads();
+      if (gi == 0)
+        for (int g = 1; g < G; ++g)
+#pragma unroll
+          for (int k = 0; k < TPT; ++k)
+            for (int c = 0; c < 4; ++c) S[k][c] += red[((g - 1) * L + li) * (4 * TPT) + 4 * k + c];
+    }
+    if (gi == 0)
+#pragma unroll
+      for (int k = 0; k < TPT; ++k)
+        if (ti[k] < t1)
+          for (int c = 0; c < 4; ++c) part[((size_t)slot * 4 + c) * N + ti[k]] = S[k][c];
   }
 }
 
@@ -286,23 +340,27 @@ __global__ __launch_bounds__(64) void k_p2p_tasks(int ntask, const int *__restri
                                                   const T *__restrict__ tgt, int N,
                                                   T kappa, T nk, double *__restrict__ part) {
   __shared__ __align__(16) T sh[kTileT * 16];
+  __shared__ double red[64 * 4 * kMaxTPT];
   const int task = xcd_task(ntask);
   if (task < 0) return;
   const int t0 = tasks[4 * task], t1 = tasks[4 * task + 1];
   const int lb = tasks[4 * task + 2], le = tasks[4 * task + 3];
   const int slot = slots[task];
-  const int tpt = min(5, (t1 - t0 + 63) / 64);
-  switch (tpt) {
-    case 1: p2p_task_body<T, NF, 1, FLOOR>(src, tgt, N, t0, t1, ranges, lb, le, kappa, nk, slot, part, sh); break;
-    case 2: p2p_task_body<T, NF, 2, FLOOR>(src, tgt, N, t0, t1, ranges, lb, le, kappa, nk, slot, part, sh); break;
-    case 3: p2p_task_body<T, NF, 3, FLOOR>(src, tgt, N, t0, t1, ranges, lb, le, kappa, nk, slot, part, sh); break;
-    case 4: p2p_task_body<T, NF, 4, FLOOR>(src, tgt, N, t0, t1, ranges, lb, le, kappa, nk, slot, part, sh); break;
-    default: p2p_task_body<T, NF, 5, FLOOR>(src, tgt, N, t0, t1, ranges, lb, le, kappa, nk, slot, part, sh); break;
+  const LaneSplit ls = lane_split(t1 - t0);
+  switch (ls.tpt) {
+#define PBMP_BODY(K)                                                                          \
+  p2p_task_body<T, NF, K, FLOOR>(src, tgt, N, t0, t1, ranges, lb, le, kappa, nk, slot, part, \
+                                 sh, red, ls.G, ls.L)
+    case 1: PBMP_BODY(1); break;
+    case 2: PBMP_BODY(2); break;
+    case 3: PBMP_BODY(3); break;
+    case 4: PBMP_BODY(4); break;
+    default: PBMP_BODY(5); break;
+#undef PBMP_BODY
   }
 }
 
 // ------------------------------------------------------------ M2P tasks
-constexpr int kChunkBoxes = 32;
 
 template <class T> __device__ inline T rsqrt_t(T x);
 template <> __device__ inline float rsqrt_t<float>(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -326,24 +384,46 @@ __global__ __launch_bounds__(64) void k_m2p_tasks(int ntask, const int *__restri
                                                   double *__restrict__ part) {
   constexpr Multi<P> mi{};
   constexpr int NC = Multi<P>::n;
-  __shared__ T smom[kChunkBoxes * 2 * NC];
-  __shared__ T scen[kChunkBoxes * 3];
+  __shared__ T smom[kM2PChunkBoxes * 2 * NC];
+  __shared__ T scen[kM2PChunkBoxes * 3];
+  __shared__ double red[64 * 4];
   const int task = xcd_task(ntask);
   if (task < 0) return;
   const int t0 = tasks[4 * task], t1 = tasks[4 * task + 1];
   const int lb = tasks[4 * task + 2], le = tasks[4 * task + 3];
   const int slot = slots[task];
   const int nb = le - lb;
+  const int nt = t1 - t0;
   for (int e = threadIdx.x; e < nb * 2 * NC; e += 64) {
     const int b = e / (2 * NC), c = e % (2 * NC);
     smom[e] = mom[(size_t)boxes[lb + b] * 2 * NC + c];
   }
   for (int e = threadIdx.x; e < nb * 3; e += 64) scen[e] = (T)center[3 * boxes[lb + e / 3] + e % 3];
+  // lanes in G groups of L = 64 / G: a group takes every G-th box for all
+  // targets; G maximises the useful fraction nt nb / (64 ceil(nt/L) ceil(nb/G))
+  int G = 1;
+  {
+    float be = 0.0f;
+    for (int g = 1; g <= 16; ++g) {
+      const int L = 64 / g;
+      const float e = (float)nt * nb / (64.0f * ((nt + L - 1) / L) * ((nb + g - 1) / g));
+      if (e > be) {
+        be = e;
+        G = g;
+      }
+    }
+  }
+  const int L = 64 / G;
+  const int gi = (int)threadIdx.x / L, li = (int)threadIdx.x - gi * L;
+  const bool active = gi < G;
   __syncthreads();
-  for (int t = t0 + threadIdx.x; t < t1; t += 64) {
-    const T x = tgt[t], y = tgt[N + t], z = tgt[2 * N + t];
+  const int iters = (nt + L - 1) / L;
+  for (int it = 0; it < iters; ++it) {
+    const int t = t0 + it * L + li;
+    const int tl = min(t, t1 - 1);
+    const T x = tgt[tl], y = tgt[N + tl], z = tgt[2 * N + tl];
     T acc[4] = {T(0), T(0), T(0), T(0)};
-    for (int b = 0; b < nb; ++b) {
+    for (int b = active ? gi : nb; b < nb; b += G) {
       const T D[3] = {x - scen[3 * b], y - scen[3 * b + 1], z - scen[3 * b + 2]};
       const T R2 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
       const T ri = rsqrt_t<T>(R2);
@@ -385,7 +465,18 @@ __global__ __launch_bounds__(64) void k_m2p_tasks(int ntask, const int *__restri
         acc[3] += ay[k] * m[NC + k];
       }
     }
-    for (int c = 0; c < 4; ++c) part[((size_t)slot * 4 + c) * N + t] = (double)acc[c];
+    double sum[4] = {(double)acc[0], (double)acc[1], (double)acc[2], (double)acc[3]};
+    if (G > 1) {
+      __syncthreads();
+      if (active && gi > 0)
+        for (int c = 0; c < 4; ++c) red[((gi - 1) * L + li) * 4 + c] = sum[c];
+      __syncthreads();
+      if (gi == 0)
+        for (int g = 1; g < G; ++g)
+          for (int c = 0; c < 4; ++c) sum[c] += red[((g - 1) * L + li) * 4 + c];
+    }
+    if (gi == 0 && t < t1)
+      for (int c = 0; c < 4; ++c) part[((size_t)slot * 4 + c) * N + t] = sum[c];
   }
 }
 

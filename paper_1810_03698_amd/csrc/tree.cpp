@@ -18,8 +18,13 @@
 namespace pbmp {
 
 namespace {
-constexpr int kP2PChunkPanels = 512;   // source panels per P2P task
-constexpr int kM2PChunkBoxes = 16;     // boxes per M2P task
+#ifndef PBMP_P2P_CHUNK
+#define PBMP_P2P_CHUNK 256
+#endif
+// source panels per P2P task: leaf ranges are cut at this size so that no
+// task is much longer than the others (the launch is short enough for the
+// longest task to set its duration)
+constexpr int kP2PChunkPanels = PBMP_P2P_CHUNK;
 }  // namespace
 
 void Tree::build(int N, const double *cen, int nf,
@@ -149,23 +154,32 @@ void Tree::build(int N, const double *cen, int nf,
   }
   // ---- tasks: (t0, t1, list begin, list end) and the partial slot each
   // writes; slots of a target leaf are 0..n-1 in a fixed order
-  std::vector<int> pt, ps, mt, ms, tsl(N, 0);
+  std::vector<int> pt, ps, mt, ms, tsl(N, 0), srcr;
   max_slots = 0;
   for (int li = 0; li < nleaf; ++li) {
     const int T = leaves[li];
     int slot = 0;
-    int a = p2p_ptr[li];
-    while (a < p2p_ptr[li + 1]) {
-      int b = a, cnt = 0;
-      while (b < p2p_ptr[li + 1] &&
-             (b == a || cnt + (end[p2p_src[b]] - start[p2p_src[b]]) <= kP2PChunkPanels)) {
-        cnt += end[p2p_src[b]] - start[p2p_src[b]];
-        ++b;
-      }
-      pt.insert(pt.end(), {start[T], end[T], a, b});
+    // the leaf's source panels, in list order, cut into tasks of at most
+    // kP2PChunkPanels panels; a task lists its source sub-ranges
+    int first = (int)(srcr.size() / 2), cnt = 0;
+    auto close_task = [&]() {
+      pt.insert(pt.end(), {start[T], end[T], first, (int)(srcr.size() / 2)});
       ps.push_back(slot++);
-      a = b;
+      first = (int)(srcr.size() / 2);
+      cnt = 0;
+    };
+    for (int a = p2p_ptr[li]; a < p2p_ptr[li + 1]; ++a) {
+      int s0 = start[p2p_src[a]];
+      const int s1 = end[p2p_src[a]];
+      while (s0 < s1) {
+        const int take = std::min(s1 - s0, kP2PChunkPanels - cnt);
+        srcr.insert(srcr.end(), {s0, s0 + take});
+        s0 += take;
+        cnt += take;
+        if (cnt == kP2PChunkPanels) close_task();
+      }
     }
+    if (cnt > 0) close_task();
     for (int c = m2p_ptr[li]; c < m2p_ptr[li + 1]; c += kM2PChunkBoxes) {
       mt.insert(mt.end(), {start[T], end[T], c, std::min(c + kM2PChunkBoxes, m2p_ptr[li + 1])});
       ms.push_back(slot++);
@@ -175,12 +189,7 @@ void Tree::build(int N, const double *cen, int nf,
   }
   n_p2p_tasks = (int)ps.size();
   n_m2p_tasks = (int)ms.size();
-  // source ranges of the P2P lists, flattened
-  std::vector<int> srcr(2 * std::max<size_t>(1, p2p_src.size()), 0);
-  for (size_t k = 0; k < p2p_src.size(); ++k) {
-    srcr[2 * k] = start[p2p_src[k]];
-    srcr[2 * k + 1] = end[p2p_src[k]];
-  }
+  if (srcr.empty()) srcr.assign(2, 0);
   std::vector<int> range(2 * (size_t)nbox), child(8 * (size_t)nbox, -1);
   for (int b = 0; b < nbox; ++b) {
     range[2 * b] = start[b];

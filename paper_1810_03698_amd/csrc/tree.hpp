@@ -7,6 +7,9 @@
 
 namespace pbmp {
 
+// boxes per M2P task (one task's moments are staged in LDS)
+constexpr int kM2PChunkBoxes = 32;
+
 struct TreeParams {
   double theta = 0.5;
   int order = 4;
@@ -33,7 +36,7 @@ class Tree {
   Dbuf<int> d_range;      // [2*nbox] start, end
   Dbuf<int> d_p2p_task;   // [4*n] t0, t1, list begin, list end (+ slot below)
   Dbuf<int> d_p2p_slot;
-  Dbuf<int> d_p2p_src;    // source leaf ranges flattened: [2*len] start, end
+  Dbuf<int> d_p2p_src;    // source sub-ranges of the P2P tasks: [2*len] start, end
   Dbuf<int> d_m2p_task;
   Dbuf<int> d_m2p_slot;
   Dbuf<int> d_m2p_box;

@@ -63,6 +63,19 @@ SYMBOLS = ["pbmp_default_options", "pbmp_create", "pbmp_set_mesh",
            "pbmp_destroy", "pbmp_kernel_stats"]
 
 
+def _torch_runtime_first():
+    """torch ships its own copy of the HIP runtime.  Two runtimes share the
+    device in one process only if torch's is initialised first (the other
+    order leaves torch without a device), so initialise it before this
+    library's when torch is present and sees a GPU."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 def load():
     """Load libpbmp.so and declare its signatures.  Raises when missing."""
     global _lib
@@ -70,6 +83,7 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libpbmp.so is not built (run __graft_entry__.build())")
+    _torch_runtime_first()
     lib = ctypes.CDLL(LIB_PATH)
     P, D, I, L = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int64
     lib.pbmp_default_options.argtypes = [ctypes.POINTER(Options)]
