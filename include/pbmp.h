@@ -115,6 +115,13 @@ typedef struct pbmp_result {
   double t_setup_ms;       /* mesh/site preparation (first solve only)     */
   double t_solve_ms;       /* wall time of pbmp_solve                      */
   double t_matvec_ms;      /* time spent in operator applications          */
+  double G_vac_kcal;       /* Coulomb energy of the vacuum state: half the
+                              sum over sites of q phi + d.grad phi +
+                              (1/6) Q:grad grad phi, phi from the other
+                              sites' permanent multipoles (unmasked) and
+                              vacuum induced dipoles (eq. energy_multipole_
+                              polarizable); G_AB - G_A - G_B of three solves
+                              is the vacuum binding energy (eq. bind_vac)  */
 } pbmp_result;
 
 /* Fill `o` with defaults: eps 1/80, kappa 0.125, 3 far nodes, eta 2,
@@ -201,6 +208,28 @@ typedef struct pbmp_kstats {
   double p2p_pairs, m2p_pairs;
 } pbmp_kstats;
 int pbmp_kernel_stats(pbmp_ctx *c, int mode, pbmp_kstats *out);
+
+/* The octree and interaction lists that pbmp_set_mesh built in treecode
+ * mode (section "The treecode algorithm"; panels binned by centroid on a
+ * 2^21 grid over the bounding cube, a cell split while it holds more than
+ * leaf_panels panels; lists per target leaf under the acceptance test
+ * R_B < theta (|c_B - c_T| - R_T)), for inspection and tests.
+ * counts[0..3] receive nbox, nleaf, the total number of M2P list entries
+ * and of P2P list entries.  Every array may be NULL (skipped); non-NULL
+ * arrays are host memory of at least
+ *   perm[N]            internal panel order -> user panel index
+ *   box_range[2 nbox]  internal panel range [start, end) of each box
+ *   box_level[nbox]    depth (root 0)
+ *   box_centre[3 nbox] expansion centre (midpoint of the far nodes' bounding box)
+ *   box_radius[2 nbox] R_B (far nodes) and R_T (centroids) about the centre
+ *   leaf_box[nleaf]    box id of each target leaf
+ *   m2p_ptr[nleaf+1], m2p_box[n_m2p]   accepted boxes of target leaf k
+ *   p2p_ptr[nleaf+1], p2p_box[n_p2p]   leaves summed directly for leaf k
+ * Returns PBMP_ESTATE when no tree was built (direct mode, or no mesh). */
+int pbmp_tree_export(pbmp_ctx *c, int64_t counts[4], int32_t *perm, int32_t *box_range,
+                     int32_t *box_level, double *box_centre, double *box_radius,
+                     int32_t *leaf_box, int32_t *m2p_ptr, int32_t *m2p_box,
+                     int32_t *p2p_ptr, int32_t *p2p_box);
 
 /* Message for the last failing call on c (never NULL). */
 const char *pbmp_last_error(const pbmp_ctx *c);

@@ -127,6 +127,21 @@ def _pack(phi, g, H):
     return out
 
 
+def vacuum_energy(xyz, q, d, Q9, alpha, mu_v, eps_in=1.0, thole_a=0.39):
+    """Coulomb energy of the vacuum state (eq. energy_multipole_polarizable:
+    the polarisation work is carried by using d in place of d + mu), with phi
+    the potential of the other sites' permanent multipoles, unmasked and
+    undamped, plus their Thole-damped vacuum induced dipoles.  Differences
+    of it over a complex and its parts give the vacuum binding energy
+    (eq. bind_vac).  kcal/mol."""
+    M = len(xyz)
+    offdiag = ~np.eye(M, dtype=bool)
+    perm = _pack(*mp.permanent_derivs(xyz, xyz, q, d, Q9, offdiag)) / eps_in
+    ind = _pack(*mp.induced_derivs(xyz, xyz, mu_v, alpha, alpha, thole_a,
+                                   offdiag)) / eps_in
+    return mp.COULOMB_KCAL * 0.5 * _apply_D(q, d, Q9, perm + ind)
+
+
 def solvation(xyz, q, d, Q9, alpha, solvent, group=None, eps_in=1.0,
               thole_a=0.39, omega=0.7, tol_debye=1e-6, maxit=1000):
     """Full polarisable solvation energy.  Returns a dict with dG (kcal/mol),
@@ -147,7 +162,8 @@ def solvation(xyz, q, d, Q9, alpha, solvent, group=None, eps_in=1.0,
     e_solv = 0.5 * _apply_D(q, d, Q9, reac)
     e_pol = 0.5 * _apply_D(q, d, Q9, ind_d - ind_v)
     dG = mp.COULOMB_KCAL * (e_solv + e_pol)
-    return dict(dG=dG, mu_diss=mu_d, mu_vac=mu_v, scf_iters=it_d,
+    return dict(dG=dG, G_vac=vacuum_energy(xyz, q, d, Q9, alpha, mu_v, eps_in, thole_a),
+                mu_diss=mu_d, mu_vac=mu_v, scf_iters=it_d,
                 scf_iters_vac=it_v, reaction=reac,
                 x=getattr(solvent, "x", None),
                 e_solv=mp.COULOMB_KCAL * e_solv, e_pol=mp.COULOMB_KCAL * e_pol)

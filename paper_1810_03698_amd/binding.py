@@ -1,7 +1,10 @@
-"""Relative binding energy (eq. rel_bind_energy) of a complex AB from its
-parts: ddG = dG_solv(AB) - dG_solv(A) - dG_solv(B), three independent
-solves through the library, and its derivative with respect to a rigid
-translation of the ligand B.
+"""Binding energies of a complex AB from its parts (thermodynamic cycle of
+the binding-energy section), three independent solves through the library:
+  relative   ddG = dG_solv(AB) - dG_solv(A) - dG_solv(B)   (eq. rel_bind_energy)
+  vacuum     dG_bind,vac = G_AB - G_A - G_B                  (eq. bind_vac)
+  dissolved  dG_bind,diss = ddG + dG_bind,vac                (eq. bind_energy)
+with G the vacuum-state Coulomb energy each solve reports, and the
+derivative of ddG with respect to a rigid translation of the ligand B.
 
 Translating B moves B's sites and the part of the complex surface that
 belongs to B; the surface of B alone translates as a whole, which leaves
@@ -37,15 +40,17 @@ def _solve(w, opts, grad):
 
 
 def relative_binding(complex_w, receptor_w, ligand_w, n_receptor, grad=True, **opts):
-    """Returns dict(ddG, dG_complex, dG_receptor, dG_ligand, grad_t [3] or
-    None, per-solve counters).  Sites of the complex are the receptor's
-    (first n_receptor) followed by the ligand's."""
+    """Returns dict(ddG, dG_bind_vac, dG_bind_diss, dG_complex, dG_receptor,
+    dG_ligand, grad_t [3] or None, per-solve results).  Sites of the complex
+    are the receptor's (first n_receptor) followed by the ligand's."""
     rAB, gAB = _solve(complex_w, opts, grad)
     rA, _ = _solve(receptor_w, opts, False)
     rB, _ = _solve(ligand_w, opts, False)
-    out = dict(ddG=rAB["dG"] - rA["dG"] - rB["dG"], dG_complex=rAB["dG"],
-               dG_receptor=rA["dG"], dG_ligand=rB["dG"], grad_t=None,
-               solves=dict(complex=rAB, receptor=rA, ligand=rB))
+    ddG = rAB["dG"] - rA["dG"] - rB["dG"]
+    vac = rAB["G_vac"] - rA["G_vac"] - rB["G_vac"]
+    out = dict(ddG=ddG, dG_bind_vac=vac, dG_bind_diss=ddG + vac,
+               dG_complex=rAB["dG"], dG_receptor=rA["dG"], dG_ligand=rB["dG"],
+               grad_t=None, solves=dict(complex=rAB, receptor=rA, ligand=rB))
     if grad:
         is_lig = np.arange(len(complex_w["q"])) >= n_receptor
         own = vertex_owner(complex_w["verts"], complex_w["xyz"], complex_w["radii"], is_lig)

@@ -143,6 +143,17 @@ int pbmp_kernel_stats(pbmp_ctx *c, int mode, pbmp_kstats *out) {
   });
 }
 
+int pbmp_tree_export(pbmp_ctx *c, int64_t counts[4], int32_t *perm, int32_t *box_range,
+                     int32_t *box_level, double *box_centre, double *box_radius,
+                     int32_t *leaf_box, int32_t *m2p_ptr, int32_t *m2p_box,
+                     int32_t *p2p_ptr, int32_t *p2p_box) {
+  return guarded(c, [&] {
+    c->rt->tree_export(counts, perm, box_range, box_level, box_centre, box_radius, leaf_box,
+                       m2p_ptr, m2p_box, p2p_ptr, p2p_box);
+    return 0;
+  });
+}
+
 const char *pbmp_last_error(const pbmp_ctx *c) {
   if (!c) return g_create_error.c_str();
   return c->err.c_str();

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <stdexcept>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/pbmp.h"
@@ -57,6 +58,10 @@ template <class T> struct Dbuf {
                                    " bytes failed");
     }
     n = count;
+  }
+  void swap(Dbuf &o) {
+    std::swap(p, o.p);
+    std::swap(n, o.n);
   }
   // grow-only allocation for scratch buffers
   void reserve(size_t count) {

@@ -466,6 +466,40 @@ __global__ void k_adj_update(int M, double omega, const double *__restrict__ E,
   }
 }
 
+
+// Potential data (phi, grad, hessian upper) at every site of the other
+// sites' permanent multipoles, unmasked and undamped (the vacuum Coulomb
+// energy uses them; eq. energy_multipole_polarizable): the hessian is the
+// dual-number derivative of the gradient.
+__global__ void k_perm_potential(int M, const double *__restrict__ xyz,
+                                 const double *__restrict__ q, const double *__restrict__ d,
+                                 const double *__restrict__ Q, double inv_eps,
+                                 double *__restrict__ out) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= M) return;
+  double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int m = 0; m < M; ++m) {
+    if (m == l) continue;
+    D3 R[3];
+    for (int a = 0; a < 3; ++a) R[a] = D3::var(xyz[3 * l + a] - xyz[3 * m + a], a);
+    D3 g[3];
+    perm_grad<D3>(R, q[m], d + 3 * m, Q + 9 * m, g);
+    const double r[3] = {R[0].v, R[1].v, R[2].v};
+    const double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    const double ri = 1.0 / sqrt(rr), ri3 = ri / rr, ri5 = ri3 / rr;
+    const double *pm = d + 3 * m, *Qm = Q + 9 * m;
+    double S = 0.0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) S += 0.5 * (Qm[3 * a + b] + Qm[3 * b + a]) * r[a] * r[b];
+    acc[0] += q[m] * ri + (pm[0] * r[0] + pm[1] * r[1] + pm[2] * r[2]) * ri3 + 0.5 * S * ri5;
+    for (int a = 0; a < 3; ++a) acc[1 + a] += g[a].v;
+    int o = 4;
+    for (int a = 0; a < 3; ++a)
+      for (int b = a; b < 3; ++b) acc[o++] += g[a].d[b];
+  }
+  for (int k = 0; k < 10; ++k) out[10 * (size_t)l + k] = acc[k] * inv_eps;
+}
+
 }  // namespace
 
 void launch_make_weights(hipStream_t s, int M, double c, const double *q, const double *d,
@@ -543,6 +577,14 @@ void launch_adj_update(hipStream_t s, int M, double omega, const double *E, cons
                        const double *J, double Jsign, double *lam, double *out2) {
   hipLaunchKernelGGL(k_adj_update, dim3(1), dim3(256), 0, s, M, omega, E, F, J, Jsign, lam,
                      out2);
+  PBMP_HIP(hipGetLastError());
+}
+
+void launch_perm_potential(hipStream_t s, int M, const double *xyz, const double *q,
+                           const double *d, const double *Q, double eps_in, double *out) {
+  if (M <= 0) return;
+  hipLaunchKernelGGL(k_perm_potential, dim3((M + 127) / 128), dim3(128), 0, s, M, xyz, q, d, Q,
+                     1.0 / eps_in, out);
   PBMP_HIP(hipGetLastError());
 }
 

@@ -141,12 +141,12 @@ __global__ __launch_bounds__(256) void k_p2m(int nf, const int *__restrict__ lea
 
 // ---------------------------------------------------------------- M2M
 // (h + t)^k = sum_{j <= k} C(k, j) t^{k-j} h^j, t = child centre - parent
-// centre; one block per parent box, one lane per coefficient.  The
+// centre; one block per box of a level (leaves return at once), one lane
+// per coefficient.  The
 // children's moments are staged in LDS first (one coalesced read), so the
 // shift itself runs at LDS latency.
 template <int P>
-__global__ __launch_bounds__(64) void k_m2m(const int *__restrict__ boxes,
-                                            const int *__restrict__ child,
+__global__ __launch_bounds__(64) void k_m2m(int base, const int *__restrict__ child,
                                             const double *__restrict__ center,
                                             double *__restrict__ mom) {
   constexpr Multi<P> mi{};
@@ -154,11 +154,12 @@ __global__ __launch_bounds__(64) void k_m2m(const int *__restrict__ boxes,
   __shared__ double tp[8][3][P + 1];
   __shared__ double cm[8][2 * NC];
   __shared__ int cid[8];
-  const int B = boxes[blockIdx.x];
+  const int B = base + (int)blockIdx.x;
   if (threadIdx.x < 8) cid[threadIdx.x] = child[8 * B + threadIdx.x];
   __syncthreads();
   int nch = 0;
   for (int cc = 0; cc < 8; ++cc) nch += cid[cc] >= 0;
+  if (nch == 0) return;  // a leaf: its moments come from P2M (uniform per block)
   if (threadIdx.x < 3 * nch) {
     const int cc = threadIdx.x / 3, d = threadIdx.x % 3;
     const double t = center[3 * cid[cc] + d] - center[3 * B + d];
@@ -206,16 +207,19 @@ __global__ void k_cast(size_t n, const double *__restrict__ a, float *__restrict
 // smaller than a wave, so the lanes are split into G groups of L = 64 / G:
 // every group holds all targets (TPT per lane) and takes every G-th source
 // panel of a tile; the groups' FP64 sums are added in LDS in a fixed order.
-// G and TPT are chosen per task to use the most lanes.
-constexpr int kTileT = 128;
-constexpr int kMaxTPT = 5;
+// G and TPT are chosen per task to use the most lanes.  The LDS tile is
+// small and the groups' sums meet through lane shuffles, so a task holds
+// 2 KB of LDS and many waves fit on a CU.
+constexpr int kTileT = 32;
+constexpr int kMaxTPT = 3;
 
 struct LaneSplit {
   int G, L, tpt;
 };
 
 // G, L = 64 / G and targets per lane for nt targets: maximise the useful
-// fraction G nt / (64 tpt) with tpt <= kMaxTPT (ties: fewer groups)
+// fraction G nt / (64 tpt) with tpt <= kMaxTPT (ties: fewer groups; a
+// leaf of more than 64 kMaxTPT targets takes several passes with G = 1)
 __device__ inline LaneSplit lane_split(int nt) {
   LaneSplit best{1, 64, min(kMaxTPT, (nt + 63) / 64)};
   float be = (float)nt / (64.0f * best.tpt * ((nt + 64 * best.tpt - 1) / (64 * best.tpt)));
@@ -236,7 +240,7 @@ template <class T, int NF, int TPT, bool FLOOR>
 __device__ void p2p_task_body(const T *__restrict__ src, const T *__restrict__ tgt,
                               int N, int t0, int t1, const int *__restrict__ ranges,
                               int lb, int le, T kappa, T nk, int slot,
-                              double *__restrict__ part, T *sh, double *red, int G, int L) {
+                              double *__restrict__ part, T *sh, int G, int L) {
   const int lane = (int)threadIdx.x;
   const int gi = lane / L, li = lane - gi * L;
   const bool active = gi < G;
@@ -311,18 +315,16 @@ __device__ void p2p_task_body(const T *__restrict__ src, const T *__restrict__ t
       }
     }
     if (G > 1) {
-      // groups 1..G-1 hand their sums to group 0 through LDS
-      __syncthreads();
-      if (active && gi > 0)
+      // group 0 adds the other groups' sums (lane li of group g is lane
+      // li + g L); every lane takes part in the shuffles
 #pragma unroll
-        for (int k = 0; k < TPT; ++k)
-          for (int c = 0; c < 4; ++c) red[((gi - 1) * L + li) * (4 * TPT) + 4 * k + c] = S[k][c];
-      __syncthreads();
-      if (gi == 0)
-        for (int g = 1; g < G; ++g)
-#pragma unroll
-          for (int k = 0; k < TPT; ++k)
-            for (int c = 0; c < 4; ++c) S[k][c] += red[((g - 1) * L + li) * (4 * TPT) + 4 * k + c];
+      for (int k = 0; k < TPT; ++k)
+        for (int c = 0; c < 4; ++c) {
+          const double v = S[k][c];
+          double acc = v;
+          for (int g = 1; g < G; ++g) acc += __shfl(v, li + g * L, 64);
+          S[k][c] = acc;
+        }
     }
     if (gi == 0)
 #pragma unroll
@@ -340,7 +342,6 @@ __global__ __launch_bounds__(64) void k_p2p_tasks(int ntask, const int *__restri
                                                   const T *__restrict__ tgt, int N,
                                                   T kappa, T nk, double *__restrict__ part) {
   __shared__ __align__(16) T sh[kTileT * 16];
-  __shared__ double red[64 * 4 * kMaxTPT];
   const int task = xcd_task(ntask);
   if (task < 0) return;
   const int t0 = tasks[4 * task], t1 = tasks[4 * task + 1];
@@ -350,12 +351,10 @@ __global__ __launch_bounds__(64) void k_p2p_tasks(int ntask, const int *__restri
   switch (ls.tpt) {
 #define PBMP_BODY(K)                                                                          \
   p2p_task_body<T, NF, K, FLOOR>(src, tgt, N, t0, t1, ranges, lb, le, kappa, nk, slot, part, \
-                                 sh, red, ls.G, ls.L)
+                                 sh, ls.G, ls.L)
     case 1: PBMP_BODY(1); break;
     case 2: PBMP_BODY(2); break;
-    case 3: PBMP_BODY(3); break;
-    case 4: PBMP_BODY(4); break;
-    default: PBMP_BODY(5); break;
+    default: PBMP_BODY(3); break;
 #undef PBMP_BODY
   }
 }
@@ -386,7 +385,6 @@ __global__ __launch_bounds__(64) void k_m2p_tasks(int ntask, const int *__restri
   constexpr int NC = Multi<P>::n;
   __shared__ T smom[kM2PChunkBoxes * 2 * NC];
   __shared__ T scen[kM2PChunkBoxes * 3];
-  __shared__ double red[64 * 4];
   const int task = xcd_task(ntask);
   if (task < 0) return;
   const int t0 = tasks[4 * task], t1 = tasks[4 * task + 1];
@@ -466,15 +464,11 @@ __global__ __launch_bounds__(64) void k_m2p_tasks(int ntask, const int *__restri
       }
     }
     double sum[4] = {(double)acc[0], (double)acc[1], (double)acc[2], (double)acc[3]};
-    if (G > 1) {
-      __syncthreads();
-      if (active && gi > 0)
-        for (int c = 0; c < 4; ++c) red[((gi - 1) * L + li) * 4 + c] = sum[c];
-      __syncthreads();
-      if (gi == 0)
-        for (int g = 1; g < G; ++g)
-          for (int c = 0; c < 4; ++c) sum[c] += red[((g - 1) * L + li) * 4 + c];
-    }
+    if (G > 1)
+      for (int c = 0; c < 4; ++c) {
+        const double v = sum[c];
+        for (int g = 1; g < G; ++g) sum[c] += __shfl(v, li + g * L, 64);
+      }
     if (gi == 0 && t < t1)
       for (int c = 0; c < 4; ++c) part[((size_t)slot * 4 + c) * N + t] = sum[c];
   }
@@ -530,11 +524,12 @@ void launch_m2p(Tree &t, hipStream_t s, const T *mom, const T *tgt, int N, T kap
 template <int P> void launch_moments_p(Tree &t, hipStream_t s, int nf, const double *src64) {
   hipLaunchKernelGGL(k_p2m<P>, dim3(t.nleaf), dim3(256), 0, s, nf, t.d_leaves.p, t.d_range.p,
                      t.d_center.p, src64, t.d_mom64.p);
-  for (size_t l = 0; l + 1 < t.level_ptr.size(); ++l) {
-    const int nb = t.level_ptr[l + 1] - t.level_ptr[l];
+  // levels bottom-up; the deepest level holds leaves only
+  for (int l = t.depth - 1; l >= 0; --l) {
+    const int nb = t.level_start[l + 1] - t.level_start[l];
     if (nb > 0)
-      hipLaunchKernelGGL(k_m2m<P>, dim3(nb), dim3(64), 0, s, t.d_leaf_boxes.p + t.level_ptr[l],
-                         t.d_child.p, t.d_center.p, t.d_mom64.p);
+      hipLaunchKernelGGL(k_m2m<P>, dim3(nb), dim3(64), 0, s, t.level_start[l], t.d_child.p,
+                         t.d_center.p, t.d_mom64.p);
   }
 }
 
@@ -595,7 +590,7 @@ void tree_apply(Tree &t, hipStream_t s, bool fp64, int nf, int N, const double *
   PBMP_HIP(hipGetLastError());
   if (clk.on) clk.end(s, e0, KernelClock::P2P, t.direct_pairs);
 
-  if (t.n_m2p_tasks > 0 && !t.m2p_box.empty()) {
+  if (t.n_m2p_tasks > 0 && t.n_m2p_entries > 0) {
     e0 = clk.on ? clk.begin(s) : nullptr;
     if (fp64)
       launch_m2p<double>(t, s, t.d_mom64.p, geo, N, kappa, 0.0, part);

@@ -1,0 +1,556 @@
+// On-device construction of the treecode's octree and interaction lists
+// (section "The treecode algorithm").
+//
+//  1. Panels are ordered by the Morton key of their centroid on a 2^21 grid
+//     over the bounding cube (radix sort of the 63-bit keys, stable, so ties
+//     keep the caller's order); every octree cell is then a contiguous range.
+//  2. The octree is built level by level: in every box of the current level
+//     that holds more than `leaf` panels, a child starts wherever the next
+//     three key bits (the octant one level down) change.  A scan of those
+//     flags numbers the children, so box ids run level by level and, within
+//     a level, in key order.
+//  3. Box geometry: the expansion centre is the midpoint of the bounding box
+//     of the box's far nodes, R_B the largest node distance from it, R_T the
+//     largest centroid distance.
+//  4. Lists per target leaf T, descending from the root: box B is accepted
+//     for M2P when |c_B - c_T| - R_T > 0 and R_B < theta (|c_B - c_T| - R_T);
+//     a leaf that fails goes to the P2P list; other boxes are opened.  A
+//     counting pass sizes everything, scans give offsets, and a second pass
+//     writes the lists, the P2P tasks (the leaf's source panels cut into
+//     chunks of at most `chunk` panels, as sub-ranges), the M2P tasks and the
+//     partial-sum slot of every task.
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "runtime.hpp"
+
+namespace pbmp {
+
+namespace {
+
+constexpr int kLevels = 21;
+constexpr int kStack = 8 * (kLevels + 1);
+
+// 21 bits -> every third bit
+__device__ inline uint64_t spread3_d(uint64_t x) {
+  x &= 0x1fffffull;
+  x = (x | x << 32) & 0x1f00000000ffffull;
+  x = (x | x << 16) & 0x1f0000ff0000ffull;
+  x = (x | x << 8) & 0x100f00f00f00f00full;
+  x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+  x = (x | x << 2) & 0x1249249249249249ull;
+  return x;
+}
+
+// centroids (caller's order) of the triangles, SoA
+__global__ void k_user_centroids(int N, const double *__restrict__ verts,
+                                 const int *__restrict__ tri, double *__restrict__ c) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const double *A = verts + 3 * tri[3 * j], *B = verts + 3 * tri[3 * j + 1],
+               *C = verts + 3 * tri[3 * j + 2];
+  for (int d = 0; d < 3; ++d) c[(size_t)d * N + j] = (A[d] + B[d] + C[d]) / 3.0;
+}
+
+// bounding box of the centroids: one block, box[0..5] = lo xyz, hi xyz
+__global__ __launch_bounds__(1024) void k_bbox(int N, const double *__restrict__ c,
+                                               double *__restrict__ box) {
+  __shared__ double red[6][1024];
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int j = threadIdx.x; j < N; j += 1024)
+    for (int d = 0; d < 3; ++d) {
+      const double v = c[(size_t)d * N + j];
+      lo[d] = fmin(lo[d], v);
+      hi[d] = fmax(hi[d], v);
+    }
+  for (int d = 0; d < 3; ++d) {
+    red[d][threadIdx.x] = lo[d];
+    red[3 + d][threadIdx.x] = hi[d];
+  }
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int d = 0; d < 3; ++d) {
+        red[d][threadIdx.x] = fmin(red[d][threadIdx.x], red[d][threadIdx.x + w]);
+        red[3 + d][threadIdx.x] = fmax(red[3 + d][threadIdx.x], red[3 + d][threadIdx.x + w]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) box[threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_morton_keys(int N, const double *__restrict__ c, const double *__restrict__ box,
+                              uint64_t *__restrict__ key, int *__restrict__ idx) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const double ext = fmax(fmax(fmax(box[3] - box[0], box[4] - box[1]), box[5] - box[2]), 1e-12);
+  uint64_t k = 0;
+  for (int d = 0; d < 3; ++d) {
+    const double u = (c[(size_t)d * N + j] - box[d]) / ext;
+    const double g = fmin(2097151.0, fmax(0.0, floor(u * 2097152.0)));
+    k |= spread3_d((uint64_t)g) << (2 - d);
+  }
+  key[j] = k;
+  idx[j] = j;
+}
+
+// ---- level-by-level octree --------------------------------------------
+struct Boxes {
+  int *start, *end, *level, *parent, *first, *nchild;
+};
+
+__global__ void k_root(Boxes b, int N, int *__restrict__ owner) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    b.start[0] = 0;
+    b.end[0] = N;
+    b.level[0] = 0;
+    b.parent[0] = -1;
+    b.first[0] = -1;
+    b.nchild[0] = 0;
+  }
+  if (i < N) owner[i] = 0;
+}
+
+// flag[i] = 1 where a child cell (level l+1) starts inside a box of level l
+// that is split
+__global__ void k_mark(int N, int l, int leaf, const uint64_t *__restrict__ key,
+                       const int *__restrict__ owner, Boxes b, int *__restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int B = owner[i];
+  int f = 0;
+  if (b.level[B] == l && b.end[B] - b.start[B] > leaf && l < kLevels) {
+    const int sh = 3 * (kLevels - 1 - l);
+    f = (i == b.start[B]) || (((key[i] >> sh) & 7ull) != ((key[i - 1] >> sh) & 7ull));
+  }
+  flag[i] = f;
+}
+
+__global__ void k_emit(int N, int l, int base, const int *__restrict__ flag,
+                       const int *__restrict__ idx, const int *__restrict__ owner, Boxes b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N || !flag[i]) return;
+  const int k = base + idx[i], P = owner[i];
+  b.start[k] = i;
+  b.level[k] = l + 1;
+  b.parent[k] = P;
+  b.first[k] = -1;
+  b.nchild[k] = 0;
+  if (i == b.start[P]) b.first[P] = k;
+}
+
+__global__ void k_ends(int base, int nnew, Boxes b) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nnew) return;
+  const int k = base + t, P = b.parent[k];
+  const bool last = (t + 1 == nnew) || b.parent[k + 1] != P;
+  b.end[k] = last ? b.end[P] : b.start[k + 1];
+  if (last) b.nchild[P] = k - b.first[P] + 1;
+}
+
+__global__ void k_owner(int N, int l, int base, const int *__restrict__ flag,
+                        const int *__restrict__ idx, Boxes b, int *__restrict__ owner) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int B = owner[i];
+  if (b.level[B] == l && b.nchild[B] > 0) owner[i] = base + idx[i] + flag[i] - 1;
+}
+
+__global__ void k_leaf_flags(int nbox, Boxes b, int *__restrict__ flag) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nbox) flag[k] = b.nchild[k] == 0;
+}
+
+__global__ void k_leaf_list(int nbox, const int *__restrict__ flag, const int *__restrict__ idx,
+                            int *__restrict__ leaves) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nbox && flag[k]) leaves[idx[k]] = k;
+}
+
+// ranges and the 8-wide child table in the layout of the product kernels
+__global__ void k_pack_boxes(int nbox, Boxes b, int *__restrict__ range,
+                             int *__restrict__ child) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nbox) return;
+  range[2 * k] = b.start[k];
+  range[2 * k + 1] = b.end[k];
+  for (int c = 0; c < 8; ++c) child[8 * k + c] = c < b.nchild[k] ? b.first[k] + c : -1;
+}
+
+// ---- box geometry: one wave per box -------------------------------------
+__device__ inline double wave_min(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__global__ __launch_bounds__(64) void k_box_geometry(int nbox, int nf, int N, Boxes b,
+                                                     const double *__restrict__ src64,
+                                                     const double *__restrict__ geo,
+                                                     double *__restrict__ center,
+                                                     double *__restrict__ radius) {
+  const int B = blockIdx.x;
+  const int s0 = b.start[B], s1 = b.end[B];
+  const int n = (s1 - s0) * nf;
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int g = threadIdx.x; g < n; g += 64) {
+    const double *y = src64 + 16 * (size_t)(s0 + g / nf) + 3 * (g % nf);
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = fmin(lo[d], y[d]);
+      hi[d] = fmax(hi[d], y[d]);
+    }
+  }
+  double c[3];
+  for (int d = 0; d < 3; ++d) c[d] = 0.5 * (wave_min(lo[d]) + wave_max(hi[d]));
+  double rb = 0.0, rt = 0.0;
+  for (int g = threadIdx.x; g < n; g += 64) {
+    const double *y = src64 + 16 * (size_t)(s0 + g / nf) + 3 * (g % nf);
+    double r2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const double t = y[d] - c[d];
+      r2 += t * t;
+    }
+    rb = fmax(rb, r2);
+  }
+  for (int j = s0 + (int)threadIdx.x; j < s1; j += 64) {
+    double r2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const double t = geo[(size_t)d * N + j] - c[d];
+      r2 += t * t;
+    }
+    rt = fmax(rt, r2);
+  }
+  rb = wave_max(rb);
+  rt = wave_max(rt);
+  if (threadIdx.x == 0) {
+    for (int d = 0; d < 3; ++d) center[3 * B + d] = c[d];
+    radius[2 * B] = sqrt(rb);
+    radius[2 * B + 1] = sqrt(rt);
+  }
+}
+
+// ---- interaction lists -------------------------------------------------
+struct ListOut {
+  // counting pass: per leaf [8]: n_m2p, n_p2p, n_sub, n_ptask, n_mtask,
+  // p2p panels, targets, spare
+  int *count;
+  // filling pass (offsets = exclusive scans of the counts)
+  const int *off_m2p, *off_p2p, *off_sub, *off_ptask, *off_mtask;
+  int *m2p_box, *p2p_box, *sub, *ptask, *pslot, *mtask, *mslot;
+  int *slots_of_box;
+};
+
+template <bool FILL>
+__global__ void k_lists(int nleaf, const int *__restrict__ leaves, Boxes b,
+                        const double *__restrict__ center, const double *__restrict__ radius,
+                        double theta, int chunk, int mchunk, ListOut out) {
+  const int li = blockIdx.x * blockDim.x + threadIdx.x;
+  if (li >= nleaf) return;
+  const int T = leaves[li];
+  const double cT[3] = {center[3 * T], center[3 * T + 1], center[3 * T + 2]};
+  const double RT = radius[2 * T + 1];
+  const int t0 = b.start[T], t1 = b.end[T];
+  int nm = 0, np = 0, nsub = 0, ntask = 0, cnt = 0, panels = 0;
+  int om = 0, op = 0, os = 0, ot = 0, firstsub = 0;
+  if (FILL) {
+    om = out.off_m2p[li];
+    op = out.off_p2p[li];
+    os = out.off_sub[li];
+    ot = out.off_ptask[li];
+    firstsub = os;
+  }
+  int stack[kStack];
+  int top = 0;
+  stack[top++] = 0;
+  while (top > 0) {
+    const int B = stack[--top];
+    double d2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const double t = center[3 * B + d] - cT[d];
+      d2 += t * t;
+    }
+    const double sep = sqrt(d2) - RT;
+    if (sep > 0.0 && radius[2 * B] < theta * sep) {
+      if (FILL) out.m2p_box[om + nm] = B;
+      ++nm;
+    } else if (b.nchild[B] == 0) {
+      if (FILL) out.p2p_box[op + np] = B;
+      ++np;
+      int s0 = b.start[B];
+      const int s1 = b.end[B];
+      panels += s1 - s0;
+      while (s0 < s1) {
+        const int take = min(s1 - s0, chunk - cnt);
+        if (FILL) {
+          out.sub[2 * (os + nsub)] = s0;
+          out.sub[2 * (os + nsub) + 1] = s0 + take;
+        }
+        ++nsub;
+        s0 += take;
+        cnt += take;
+        if (cnt == chunk) {
+          if (FILL) {
+            int *tk = out.ptask + 4 * (ot + ntask);
+            tk[0] = t0;
+            tk[1] = t1;
+            tk[2] = firstsub;
+            tk[3] = os + nsub;
+            out.pslot[ot + ntask] = ntask;
+            firstsub = os + nsub;
+          }
+          ++ntask;
+          cnt = 0;
+        }
+      }
+    } else {
+      for (int c = b.nchild[B] - 1; c >= 0; --c) stack[top++] = b.first[B] + c;
+    }
+  }
+  if (cnt > 0) {
+    if (FILL) {
+      int *tk = out.ptask + 4 * (ot + ntask);
+      tk[0] = t0;
+      tk[1] = t1;
+      tk[2] = firstsub;
+      tk[3] = os + nsub;
+      out.pslot[ot + ntask] = ntask;
+    }
+    ++ntask;
+  }
+  const int nmt = (nm + mchunk - 1) / mchunk;
+  if (FILL) {
+    const int omt = out.off_mtask[li];
+    for (int k = 0; k < nmt; ++k) {
+      int *tk = out.mtask + 4 * (omt + k);
+      tk[0] = t0;
+      tk[1] = t1;
+      tk[2] = om + k * mchunk;
+      tk[3] = om + min((k + 1) * mchunk, nm);
+      out.mslot[omt + k] = ntask + k;
+    }
+    out.slots_of_box[T] = ntask + nmt;
+  } else {
+    int *c = out.count + 8 * (size_t)li;
+    c[0] = nm;
+    c[1] = np;
+    c[2] = nsub;
+    c[3] = ntask;
+    c[4] = nmt;
+    c[5] = panels;
+    c[6] = t1 - t0;
+    c[7] = 0;
+  }
+}
+
+__global__ void k_column(int n, const int *__restrict__ count, int c, int *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = count[8 * (size_t)i + c];
+}
+
+__global__ void k_target_slots(int N, const int *__restrict__ owner,
+                               const int *__restrict__ slots_of_box, int *__restrict__ tsl) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) tsl[i] = slots_of_box[owner[i]];
+}
+
+inline dim3 grid_for(size_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
+
+// exclusive scan of n ints on the device; returns the total
+int exclusive_scan_total(hipStream_t s, const int *in, int *out, int n, Dbuf<char> &tmp) {
+  if (n <= 0) return 0;
+  size_t bytes = 0;
+  PBMP_HIP(rocprim::exclusive_scan(nullptr, bytes, in, out, 0, (size_t)n,
+                                   rocprim::plus<int>(), s));
+  tmp.reserve(std::max<size_t>(bytes, 1));
+  PBMP_HIP(rocprim::exclusive_scan(tmp.p, bytes, in, out, 0, (size_t)n,
+                                   rocprim::plus<int>(), s));
+  int last[2];
+  PBMP_HIP(hipMemcpyAsync(&last[0], out + n - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  PBMP_HIP(hipMemcpyAsync(&last[1], in + n - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  PBMP_HIP(hipStreamSynchronize(s));
+  return last[0] + last[1];
+}
+
+}  // namespace
+
+void morton_order_device(hipStream_t s, int N, const double *verts, const int *tri_user,
+                         int *perm, uint64_t *key_sorted) {
+  Dbuf<double> cen, box;
+  Dbuf<uint64_t> key;
+  Dbuf<int> idx;
+  Dbuf<char> tmp;
+  cen.alloc(3 * (size_t)N);
+  box.alloc(6);
+  key.alloc(N);
+  idx.alloc(N);
+  hipLaunchKernelGGL(k_user_centroids, grid_for(N), dim3(256), 0, s, N, verts, tri_user, cen.p);
+  hipLaunchKernelGGL(k_bbox, dim3(1), dim3(1024), 0, s, N, cen.p, box.p);
+  hipLaunchKernelGGL(k_morton_keys, grid_for(N), dim3(256), 0, s, N, cen.p, box.p, key.p, idx.p);
+  PBMP_HIP(hipGetLastError());
+  size_t bytes = 0;
+  PBMP_HIP(rocprim::radix_sort_pairs(nullptr, bytes, key.p, key_sorted, idx.p, perm, (size_t)N,
+                                     0, 63, s));
+  tmp.alloc(std::max<size_t>(bytes, 1));
+  PBMP_HIP(rocprim::radix_sort_pairs(tmp.p, bytes, key.p, key_sorted, idx.p, perm, (size_t)N, 0,
+                                     63, s));
+  PBMP_HIP(hipStreamSynchronize(s));
+}
+
+void Tree::build_device(int N, int nf, const uint64_t *key, const double *geo,
+                        const double *src64, hipStream_t s) {
+  ncoef = (prm.order + 1) * (prm.order + 2) * (prm.order + 3) / 6;
+  Dbuf<int> owner, flag, idx;
+  Dbuf<char> tmp;
+  owner.alloc(N);
+  flag.alloc(N);
+  idx.alloc(N);
+  // box arrays with room to grow
+  int cap = std::max(64, 2 * N / std::max(1, prm.leaf) + 64);
+  auto alloc_boxes = [&](int c) {
+    Dbuf<int> *arr[6] = {&d_start, &d_end, &d_level, &d_parent, &d_first, &d_nchild};
+    for (Dbuf<int> *a : arr) {
+      Dbuf<int> nb;
+      nb.alloc(c);
+      if (a->n) PBMP_HIP(hipMemcpyAsync(nb.p, a->p, sizeof(int) * a->n,
+                                        hipMemcpyDeviceToDevice, s));
+      PBMP_HIP(hipStreamSynchronize(s));
+      a->swap(nb);
+    }
+  };
+  d_start.release();
+  d_end.release();
+  d_level.release();
+  d_parent.release();
+  d_first.release();
+  d_nchild.release();
+  alloc_boxes(cap);
+  auto view = [&]() {
+    return Boxes{d_start.p, d_end.p, d_level.p, d_parent.p, d_first.p, d_nchild.p};
+  };
+  hipLaunchKernelGGL(k_root, grid_for(N), dim3(256), 0, s, view(), N, owner.p);
+  nbox = 1;
+  depth = 0;
+  level_start.assign({0, 1});
+  for (int l = 0; l < kLevels; ++l) {
+    hipLaunchKernelGGL(k_mark, grid_for(N), dim3(256), 0, s, N, l, prm.leaf, key, owner.p,
+                       view(), flag.p);
+    const int nnew = exclusive_scan_total(s, flag.p, idx.p, N, tmp);
+    if (nnew == 0) break;
+    if (nbox + nnew > cap) {
+      cap = std::max(2 * cap, nbox + nnew + 64);
+      alloc_boxes(cap);
+    }
+    hipLaunchKernelGGL(k_emit, grid_for(N), dim3(256), 0, s, N, l, nbox, flag.p, idx.p,
+                       owner.p, view());
+    hipLaunchKernelGGL(k_ends, grid_for(nnew), dim3(256), 0, s, nbox, nnew, view());
+    hipLaunchKernelGGL(k_owner, grid_for(N), dim3(256), 0, s, N, l, nbox, flag.p, idx.p,
+                       view(), owner.p);
+    PBMP_HIP(hipGetLastError());
+    nbox += nnew;
+    depth = l + 1;
+    level_start.push_back(nbox);
+  }
+  // leaves
+  Dbuf<int> bflag, bidx;
+  bflag.alloc(nbox);
+  bidx.alloc(nbox);
+  hipLaunchKernelGGL(k_leaf_flags, grid_for(nbox), dim3(256), 0, s, nbox, view(), bflag.p);
+  nleaf = exclusive_scan_total(s, bflag.p, bidx.p, nbox, tmp);
+  d_leaves.alloc(nleaf);
+  hipLaunchKernelGGL(k_leaf_list, grid_for(nbox), dim3(256), 0, s, nbox, bflag.p, bidx.p,
+                     d_leaves.p);
+  d_range.alloc(2 * (size_t)nbox);
+  d_child.alloc(8 * (size_t)nbox);
+  hipLaunchKernelGGL(k_pack_boxes, grid_for(nbox), dim3(256), 0, s, nbox, view(), d_range.p,
+                     d_child.p);
+  // geometry
+  d_center.alloc(3 * (size_t)nbox);
+  d_radius.alloc(2 * (size_t)nbox);
+  hipLaunchKernelGGL(k_box_geometry, dim3(nbox), dim3(64), 0, s, nbox, nf, N, view(), src64,
+                     geo, d_center.p, d_radius.p);
+  PBMP_HIP(hipGetLastError());
+  // lists: count, scan, fill
+  Dbuf<int> cnt, col, off[5];
+  cnt.alloc(8 * (size_t)nleaf);
+  col.alloc(nleaf);
+  ListOut lo{};
+  lo.count = cnt.p;
+  hipLaunchKernelGGL(k_lists<false>, grid_for(nleaf, 64), dim3(64), 0, s, nleaf, d_leaves.p,
+                     view(), d_center.p, d_radius.p, prm.theta, kP2PChunkPanels,
+                     kM2PChunkBoxes, lo);
+  PBMP_HIP(hipGetLastError());
+  int tot[5];
+  for (int c = 0; c < 5; ++c) {
+    off[c].alloc(nleaf + 1);
+    hipLaunchKernelGGL(k_column, grid_for(nleaf), dim3(256), 0, s, nleaf, cnt.p, c, col.p);
+    tot[c] = exclusive_scan_total(s, col.p, off[c].p, nleaf, tmp);
+    PBMP_HIP(hipMemcpyAsync(off[c].p + nleaf, &tot[c], sizeof(int), hipMemcpyHostToDevice, s));
+    PBMP_HIP(hipStreamSynchronize(s));
+  }
+  n_m2p_entries = tot[0];
+  n_p2p_entries = tot[1];
+  n_p2p_tasks = tot[3];
+  n_m2p_tasks = tot[4];
+  d_m2p_box.alloc(std::max(1, tot[0]));
+  d_p2p_box.alloc(std::max(1, tot[1]));
+  d_p2p_src.alloc(2 * (size_t)std::max(1, tot[2]));
+  d_p2p_task.alloc(4 * (size_t)std::max(1, tot[3]));
+  d_p2p_slot.alloc(std::max(1, tot[3]));
+  d_m2p_task.alloc(4 * (size_t)std::max(1, tot[4]));
+  d_m2p_slot.alloc(std::max(1, tot[4]));
+  Dbuf<int> slots_of_box;
+  slots_of_box.alloc(nbox);
+  lo.off_m2p = off[0].p;
+  lo.off_p2p = off[1].p;
+  lo.off_sub = off[2].p;
+  lo.off_ptask = off[3].p;
+  lo.off_mtask = off[4].p;
+  lo.m2p_box = d_m2p_box.p;
+  lo.p2p_box = d_p2p_box.p;
+  lo.sub = d_p2p_src.p;
+  lo.ptask = d_p2p_task.p;
+  lo.pslot = d_p2p_slot.p;
+  lo.mtask = d_m2p_task.p;
+  lo.mslot = d_m2p_slot.p;
+  lo.slots_of_box = slots_of_box.p;
+  hipLaunchKernelGGL(k_lists<true>, grid_for(nleaf, 64), dim3(64), 0, s, nleaf, d_leaves.p,
+                     view(), d_center.p, d_radius.p, prm.theta, kP2PChunkPanels,
+                     kM2PChunkBoxes, lo);
+  d_tslots.alloc(N);
+  hipLaunchKernelGGL(k_target_slots, grid_for(N), dim3(256), 0, s, N, owner.p, slots_of_box.p,
+                     d_tslots.p);
+  PBMP_HIP(hipGetLastError());
+  d_m2p_ptr.alloc(nleaf + 1);
+  d_p2p_ptr.alloc(nleaf + 1);
+  PBMP_HIP(hipMemcpyAsync(d_m2p_ptr.p, off[0].p, sizeof(int) * (nleaf + 1),
+                          hipMemcpyDeviceToDevice, s));
+  PBMP_HIP(hipMemcpyAsync(d_p2p_ptr.p, off[1].p, sizeof(int) * (nleaf + 1),
+                          hipMemcpyDeviceToDevice, s));
+  // per-product work counts and the largest slot count (host bookkeeping
+  // for launches and counters)
+  std::vector<int> h(8 * (size_t)nleaf);
+  cnt.download(h.data(), h.size(), s);
+  PBMP_HIP(hipStreamSynchronize(s));
+  direct_pairs = m2p_pairs = 0.0;
+  max_slots = 0;
+  for (int k = 0; k < nleaf; ++k) {
+    const int *c = &h[8 * (size_t)k];
+    direct_pairs += (double)c[6] * c[5] * nf;
+    m2p_pairs += (double)c[6] * c[0];
+    max_slots = std::max(max_slots, c[3] + c[4]);
+  }
+  d_mom64.alloc((size_t)nbox * 2 * ncoef);
+  d_mom32.alloc((size_t)nbox * 2 * ncoef);
+  tree_upload_exponents(*this, s);
+  PBMP_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace pbmp

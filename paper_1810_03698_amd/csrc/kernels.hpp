@@ -99,6 +99,9 @@ void launch_scf_update(hipStream_t s, int M, const double *alpha,
 
 // e[0] = 1/2 sum D_l (4 pi reac_l), e[1] = 1/2 sum D_l ind_l  with D_l =
 // q + d.grad + (1/6) Q:grad grad (single block, fixed order).
+// potential data [M,10] of the other sites' permanent multipoles (unmasked)
+void launch_perm_potential(hipStream_t s, int M, const double *xyz, const double *q,
+                           const double *d, const double *Q, double eps_in, double *out);
 void launch_energy(hipStream_t s, int M, const double *q, const double *d,
                    const double *Q9, const double *reac10, const double *ind10,
                    double *e);

@@ -48,16 +48,6 @@ bool finite_all(const std::vector<double> &v) {
   return true;
 }
 
-uint64_t spread3(uint64_t x) {  // 21 bits -> every third bit
-  x &= 0x1fffff;
-  x = (x | x << 32) & 0x1f00000000ffffULL;
-  x = (x | x << 16) & 0x1f0000ff0000ffULL;
-  x = (x | x << 8) & 0x100f00f00f00f00fULL;
-  x = (x | x << 4) & 0x10c30c30c30c30c3ULL;
-  x = (x | x << 2) & 0x1249249249249249ULL;
-  return x;
-}
-
 // Uniform-grid neighbour search: for every query point q_l, the panels j
 // with |q_l - c_j| < radius(l, j) (strict).  The grid cell is at least the
 // largest radius.
@@ -256,50 +246,36 @@ void Runtime::set_mesh(int64_t nv, const double *verts, int64_t nt,
     PBMP_REQUIRE(std::binary_search(edges.begin(), edges.end(), b * Nv + a),
                  PBMP_EMESH, "mesh not closed (edge without its reverse)");
   }
-  // --- enclosed volume, centroids for the Morton order
+  // --- enclosed volume
   double vol = 0.0;
-  std::vector<double> c(3 * (size_t)N);
   for (int j = 0; j < N; ++j) {
     const double *A = &hv[3 * ht[3 * j]], *B = &hv[3 * ht[3 * j + 1]],
                  *C = &hv[3 * ht[3 * j + 2]];
     vol += A[0] * (B[1] * C[2] - B[2] * C[1]) + A[1] * (B[2] * C[0] - B[0] * C[2]) +
            A[2] * (B[0] * C[1] - B[1] * C[0]);
-    for (int d = 0; d < 3; ++d) c[3 * j + d] = (A[d] + B[d] + C[d]) / 3.0;
   }
   PBMP_REQUIRE(vol > 0, PBMP_EMESH, "enclosed volume not positive (inward orientation)");
-  // --- Morton order of the centroids
-  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-  for (int j = 0; j < N; ++j)
-    for (int d = 0; d < 3; ++d) {
-      lo[d] = std::min(lo[d], c[3 * j + d]);
-      hi[d] = std::max(hi[d], c[3 * j + d]);
-    }
-  double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-12});
-  std::vector<std::pair<uint64_t, int>> kv(N);
-  for (int j = 0; j < N; ++j) {
-    uint64_t k = 0;
-    for (int d = 0; d < 3; ++d) {
-      const double u = (c[3 * j + d] - lo[d]) / ext;
-      const uint64_t q = (uint64_t)std::min(2097151.0, std::max(0.0, u * 2097152.0));
-      k |= spread3(q) << (2 - d);
-    }
-    kv[j] = {k, j};
+  // --- Morton order of the centroids (device radix sort)
+  verts_.upload(hv.data(), hv.size(), s_);
+  {
+    Dbuf<int> tri_user;
+    tri_user.upload(ht.data(), ht.size(), s_);
+    d_perm_.alloc(N);
+    keys_.alloc(N);
+    morton_order_device(s_, N, verts_.p, tri_user.p, d_perm_.p, keys_.p);
   }
-  std::stable_sort(kv.begin(), kv.end());
   perm_.resize(N);
+  d_perm_.download(perm_.data(), N, s_);
+  sync();
   h_tri_.resize(3 * (size_t)N);
-  for (int i = 0; i < N; ++i) {
-    perm_[i] = kv[i].second;
+  for (int i = 0; i < N; ++i)
     for (int k = 0; k < 3; ++k) h_tri_[3 * i + k] = ht[3 * perm_[i] + k];
-  }
   N_ = N;
   Nv_ = Nv;
   h_verts_ = hv;
   solved_ = false;
   M_ = 0;
-  verts_.upload(hv.data(), hv.size(), s_);
   tri_.upload(h_tri_.data(), h_tri_.size(), s_);
-  d_perm_.upload(perm_.data(), N, s_);
   geo_.alloc(7 * (size_t)N);
   src64_.alloc(16 * (size_t)N);
   src32_.alloc(16 * (size_t)N);
@@ -340,19 +316,11 @@ void Runtime::set_mesh(int64_t nv, const double *verts, int64_t nt,
                  (o.mode == PBMP_MODE_AUTO && N > 20000);
   tree_.reset();
   if (tree_active_) {
-    std::vector<double> nodes(3 * (size_t)ru_.nf * N);
-    std::vector<double> h_src(16 * (size_t)N);
-    src64_.download(h_src.data(), h_src.size(), s_);
-    sync();
-    for (int j = 0; j < N; ++j)
-      for (int q = 0; q < ru_.nf; ++q)
-        for (int d = 0; d < 3; ++d)
-          nodes[(3 * (size_t)j + q) * 3 + d] = h_src[16 * (size_t)j + 3 * q + d];
     tree_.reset(new Tree());
     tree_->prm.theta = o.theta;
     tree_->prm.order = o.order_P;
     tree_->prm.leaf = o.leaf_panels;
-    tree_->build(N, h_geo_.data(), ru_.nf, nodes, s_);
+    tree_->build_device(N, ru_.nf, keys_.p, geo_.p, src64_.p, s_);
   }
   alloc_work();
   sync();
@@ -499,10 +467,12 @@ void Runtime::set_sites(int64_t m, const double *xyz, const double *q,
   Eind_.alloc(3 * (size_t)M);
   reac_.alloc(10 * (size_t)M);
   ind_.alloc(10 * (size_t)M);
+  vac_perm_.alloc(10 * (size_t)M);
+  vac_ind_.alloc(10 * (size_t)M);
   p_.alloc(3 * (size_t)M);
   f_.alloc(N_);
   dmu2_.alloc(1);
-  e_.alloc(2);
+  e_.alloc(4);
   ro_chunks_ = std::max(1, std::min(64, (2048 + M - 1) / M));
   ro_chunks_ = std::min(ro_chunks_, std::max(1, N_ / 256));
   rpart_.alloc((size_t)ro_chunks_ * M * 10);
@@ -729,13 +699,19 @@ int Runtime::solve(pbmp_result *r) {
   launch_axpy(s_, 3 * M_, -1.0, mu_v_.p, p_.p);
   launch_induced(s_, true, M_, sxyz_.p, p_.p, salpha_.p, o.thole_a, o.eps_in, ind_.p);
   launch_energy(s_, M_, sq_.p, sd_.p, sQ_.p, reac_.p, ind_.p, e_.p);
-  double e[2];
+  // vacuum Coulomb energy (the same energy form with phi = potential of
+  // the other sites' permanent multipoles and vacuum induced dipoles)
+  launch_perm_potential(s_, M_, sxyz_.p, sq_.p, sd_.p, sQ_.p, o.eps_in, vac_perm_.p);
+  launch_induced(s_, true, M_, sxyz_.p, mu_v_.p, salpha_.p, o.thole_a, o.eps_in, vac_ind_.p);
+  launch_energy(s_, M_, sq_.p, sd_.p, sQ_.p, vac_perm_.p, vac_ind_.p, e_.p + 2);
+  double e[4];
   PBMP_HIP(hipMemcpyAsync(e, e_.p, sizeof(e), hipMemcpyDeviceToHost, s_));
   sync();
   const double C = coulomb_kcal();
   r->dG_solv_kcal = C * e[0];
   r->dG_pol_kcal = C * e[1];
   r->dG_kcal = C * (e[0] + e[1]);
+  r->G_vac_kcal = C * (e[2] + e[3]);
   r->scf_iters = std::abs(it_d);
   r->scf_iters_vac = std::abs(it_v);
   r->gmres_iters_total = gmres_iters_;

@@ -51,6 +51,10 @@ class Runtime {
   void matvec_user(const double *x, double *y, int transpose, int where);
   void rhs_user(const double *p, double *f, int where);
   void site_fields_user(const double *x, double *out, int where);
+  void tree_export(int64_t counts[4], int32_t *perm, int32_t *box_range, int32_t *box_level,
+                   double *box_centre, double *box_radius, int32_t *leaf_box,
+                   int32_t *m2p_ptr, int32_t *m2p_box, int32_t *p2p_ptr,
+                   int32_t *p2p_box) const;
   int backward(double dGbar, double *g_xyz, double *g_q, double *g_d,
                double *g_Q, double *g_verts, int where);
 
@@ -69,6 +73,7 @@ class Runtime {
   int N_ = 0, Nv_ = 0;
   std::vector<int> perm_;  // internal -> user panel index
   Dbuf<int> d_perm_;
+  Dbuf<uint64_t> keys_;  // Morton keys in internal order
   Dbuf<double> verts_;
   Dbuf<int> tri_;
   Dbuf<double> geo_, src64_;
@@ -97,6 +102,7 @@ class Runtime {
   Dbuf<double> V_, w_, z_, ax_, b_, x_, hbuf_, partial_, ybuf_, tmp_;
   Dbuf<double> mu_d_, mu_v_, Eperm_, Eind_, reac_, ind_, p_, f_, dmu2_, e_;
   Dbuf<double> io_a_, io_b_;  // permutation staging
+  Dbuf<double> vac_perm_, vac_ind_;  // vacuum-state potential data [10M]
   bool solved_ = false;
   int gmres_iters_ = 0, matvecs_ = 0;
   double last_relres_ = 0.0;

@@ -1,4 +1,5 @@
-// Octree over the panels (internal Morton order) for the treecode product.
+// Octree over the panels (internal Morton order) for the treecode product,
+// built on the device (k_treebuild.hip).
 #pragma once
 
 #include <vector>
@@ -8,7 +9,11 @@
 namespace pbmp {
 
 // boxes per M2P task (one task's moments are staged in LDS)
-constexpr int kM2PChunkBoxes = 32;
+constexpr int kM2PChunkBoxes = 16;
+// source panels per P2P task: a leaf's source list is cut at this size so
+// that no task is much longer than the others (the launch is short enough
+// for the longest task to set its duration)
+constexpr int kP2PChunkPanels = 256;
 
 struct TreeParams {
   double theta = 0.5;
@@ -20,39 +25,43 @@ class Tree {
  public:
   TreeParams prm;
   int nbox = 0, nleaf = 0, ncoef = 0, depth = 0;
-  // host topology
-  std::vector<int> start, end, parent, level, first_child, nchild;
-  std::vector<double> center, radius, tradius;  // [3*nbox], [nbox], [nbox]
-  std::vector<int> leaves;                      // box ids of leaves
-  // interaction lists per target leaf (CSR over leaf index)
-  std::vector<int> p2p_ptr, p2p_src;  // source leaf box ids
-  std::vector<int> m2p_ptr, m2p_box;  // accepted boxes
-  // tasks
+  std::vector<int> level_start;  // boxes of level l are [level_start[l], level_start[l+1])
+  // tasks and list sizes
   int n_p2p_tasks = 0, n_m2p_tasks = 0, max_slots = 0;
+  int n_m2p_entries = 0, n_p2p_entries = 0;
   double direct_pairs = 0.0, m2p_pairs = 0.0;  // per product (nodes / boxes)
 
-  // device data
-  Dbuf<double> d_center;  // [3*nbox]
+  // boxes (ids level by level, key order within a level)
+  Dbuf<int> d_start, d_end, d_level, d_parent, d_first, d_nchild;
   Dbuf<int> d_range;      // [2*nbox] start, end
-  Dbuf<int> d_p2p_task;   // [4*n] t0, t1, list begin, list end (+ slot below)
+  Dbuf<int> d_child;      // [8*nbox] child ids (-1 none)
+  Dbuf<double> d_center;  // [3*nbox] expansion centres
+  Dbuf<double> d_radius;  // [2*nbox] R_B (far nodes), R_T (centroids)
+  Dbuf<int> d_leaves;     // [nleaf] leaf box ids (the target leaves)
+  // lists per target leaf (CSR over the leaf index)
+  Dbuf<int> d_m2p_ptr, d_m2p_box;  // accepted boxes
+  Dbuf<int> d_p2p_ptr, d_p2p_box;  // leaves summed directly
+  // tasks
+  Dbuf<int> d_p2p_task;   // [4*n] t0, t1, sub-range begin, end
   Dbuf<int> d_p2p_slot;
   Dbuf<int> d_p2p_src;    // source sub-ranges of the P2P tasks: [2*len] start, end
-  Dbuf<int> d_m2p_task;
+  Dbuf<int> d_m2p_task;   // [4*n] t0, t1, list begin, end
   Dbuf<int> d_m2p_slot;
-  Dbuf<int> d_m2p_box;
   Dbuf<int> d_tslots;     // [N] number of slots of the target's leaf
-  Dbuf<int> d_leaves;     // leaf box ids
-  Dbuf<int> d_leaf_boxes; // boxes with moments needed, by level (bottom-up)
-  std::vector<int> level_ptr;  // CSR of d_leaf_boxes per level
-  Dbuf<int> d_child;      // [8*nbox] child ids (-1 none)
   Dbuf<double> d_mom64;   // [nbox][2][ncoef]
   Dbuf<float> d_mom32;    // [nbox][2][ncoef]
   Dbuf<int> d_monos;      // [3*ncoef] exponents
 
-  // Build from Morton-sorted panel centroids and far-field nodes (host data).
-  void build(int N, const double *cen /*SoA 3N*/, int nf,
-             const std::vector<double> &nodes /*[N][nf][3]*/, hipStream_t s);
+  // Build from the Morton keys of the panels in internal (sorted) order,
+  // the centroids (geo SoA) and far nodes (src64 records), all on device.
+  void build_device(int N, int nf, const uint64_t *key, const double *geo,
+                    const double *src64, hipStream_t s);
 };
+
+// Morton order of the panels on the device: perm[i] = caller's index of the
+// i-th panel, key_sorted[i] its key (tri_user: the caller's triangles)
+void morton_order_device(hipStream_t s, int N, const double *verts, const int *tri_user,
+                         int *perm, uint64_t *key_sorted);
 
 // upload the multi-index exponent table of the chosen order (d_monos)
 void tree_upload_exponents(Tree &t, hipStream_t s);

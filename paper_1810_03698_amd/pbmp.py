@@ -44,7 +44,8 @@ class Result(ctypes.Structure):
                 ("scf_iters", ctypes.c_int), ("scf_iters_vac", ctypes.c_int),
                 ("gmres_iters_total", ctypes.c_int), ("matvecs", ctypes.c_int),
                 ("final_relres", ctypes.c_double), ("t_setup_ms", ctypes.c_double),
-                ("t_solve_ms", ctypes.c_double), ("t_matvec_ms", ctypes.c_double)]
+                ("t_solve_ms", ctypes.c_double), ("t_matvec_ms", ctypes.c_double),
+                ("G_vac_kcal", ctypes.c_double)]
 
 
 class KernelStats(ctypes.Structure):
@@ -60,7 +61,7 @@ _lib = None
 SYMBOLS = ["pbmp_default_options", "pbmp_create", "pbmp_set_mesh",
            "pbmp_set_sites", "pbmp_solve", "pbmp_matvec", "pbmp_rhs",
            "pbmp_site_fields", "pbmp_backward", "pbmp_last_error",
-           "pbmp_destroy", "pbmp_kernel_stats"]
+           "pbmp_destroy", "pbmp_kernel_stats", "pbmp_tree_export"]
 
 
 def _torch_runtime_first():
@@ -101,9 +102,10 @@ def load():
     lib.pbmp_destroy.argtypes = [P]
     lib.pbmp_destroy.restype = None
     lib.pbmp_kernel_stats.argtypes = [P, I, ctypes.POINTER(KernelStats)]
+    lib.pbmp_tree_export.argtypes = [P] * 12
     for name in ("pbmp_create", "pbmp_set_mesh", "pbmp_set_sites", "pbmp_solve",
                  "pbmp_matvec", "pbmp_rhs", "pbmp_site_fields", "pbmp_backward",
-                 "pbmp_kernel_stats"):
+                 "pbmp_kernel_stats", "pbmp_tree_export"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -230,7 +232,7 @@ class Solver:
             r.mu_diss, r.mu_vac = keep["mu_diss"].ctypes.data, keep["mu_vac"].ctypes.data
         rc = self._check(self.lib.pbmp_solve(self.ctx, ctypes.byref(r)), allow_warn=True)
         out = dict(status=rc, dG=r.dG_kcal, dG_solv=r.dG_solv_kcal,
-                   dG_pol=r.dG_pol_kcal, scf_iters=r.scf_iters,
+                   dG_pol=r.dG_pol_kcal, G_vac=r.G_vac_kcal, scf_iters=r.scf_iters,
                    scf_iters_vac=r.scf_iters_vac, gmres_iters=r.gmres_iters_total,
                    matvecs=r.matvecs, relres=r.final_relres,
                    t_setup_ms=r.t_setup_ms, t_solve_ms=r.t_solve_ms,
@@ -296,6 +298,28 @@ class Solver:
         mode = -1 if enable is None else int(bool(enable))
         self._check(self.lib.pbmp_kernel_stats(self.ctx, mode, ctypes.byref(st)))
         return {k: getattr(st, k) for k, _ in KernelStats._fields_}
+
+    def tree(self):
+        """The treecode octree and interaction lists of the current mesh
+        (numpy arrays; see pbmp_tree_export)."""
+        counts = np.zeros(4, dtype=np.int64)
+        self._check(self.lib.pbmp_tree_export(self.ctx, counts.ctypes.data, *([None] * 10)))
+        nbox, nleaf, nm, npp = (int(v) for v in counts)
+        out = dict(perm=np.empty(self.nt, np.int32), box_range=np.empty(2 * nbox, np.int32),
+                   box_level=np.empty(nbox, np.int32), box_centre=np.empty(3 * nbox),
+                   box_radius=np.empty(2 * nbox), leaf_box=np.empty(nleaf, np.int32),
+                   m2p_ptr=np.empty(nleaf + 1, np.int32), m2p_box=np.empty(max(nm, 1), np.int32),
+                   p2p_ptr=np.empty(nleaf + 1, np.int32), p2p_box=np.empty(max(npp, 1), np.int32))
+        order = ("perm", "box_range", "box_level", "box_centre", "box_radius", "leaf_box",
+                 "m2p_ptr", "m2p_box", "p2p_ptr", "p2p_box")
+        self._check(self.lib.pbmp_tree_export(self.ctx, counts.ctypes.data,
+                                              *[out[k].ctypes.data for k in order]))
+        out["box_range"] = out["box_range"].reshape(nbox, 2)
+        out["box_centre"] = out["box_centre"].reshape(nbox, 3)
+        out["box_radius"] = out["box_radius"].reshape(nbox, 2)
+        out["m2p_box"] = out["m2p_box"][:nm]
+        out["p2p_box"] = out["p2p_box"][:npp]
+        return out
 
 
 def _empty_like_torch(t, n=None):

@@ -121,6 +121,7 @@ def test_solve_fp64_matches_oracle(cfg0):
           got["gmres_iters"])
     assert got["status"] == 0
     assert rel < 1e-10
+    assert abs(got["G_vac"] - ref["G_vac"]) < 1e-12 * abs(ref["G_vac"])
     assert got["scf_iters"] == ref["scf_iters"]
     assert np.abs(got["mu_diss"] - ref["mu_diss"]).max() < 1e-10 * np.abs(ref["mu_diss"]).max()
     assert np.abs(got["mu_vac"] - ref["mu_vac"]).max() < 1e-12 * np.abs(ref["mu_vac"]).max()

@@ -107,3 +107,62 @@ def test_tree_on_ragged_molecule():
         err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
         print(precision, err)
         assert err < 5e-4
+
+
+def _tree_sets(t):
+    """Library tree as panel sets (user indices) and per-leaf list sets."""
+    perm = t["perm"]
+    boxes = [frozenset(perm[a:b].tolist()) for a, b in t["box_range"]]
+    lists = {}
+    for k, lb in enumerate(t["leaf_box"]):
+        m2p = {boxes[b] for b in t["m2p_box"][t["m2p_ptr"][k]:t["m2p_ptr"][k + 1]]}
+        p2p = {boxes[b] for b in t["p2p_box"][t["p2p_ptr"][k]:t["p2p_ptr"][k + 1]]}
+        lists[boxes[lb]] = (m2p, p2p)
+    return boxes, lists
+
+
+@pytest.mark.parametrize("name,leaf,theta", [("sphere_5120", 64, 0.5),
+                                             ("ragged", 50, 0.5),
+                                             ("sphere_5120", 300, 0.7)])
+def test_tree_lists_match_oracle(name, leaf, theta, sph5120):
+    """Octree cells, expansion centres, radii and every interaction list
+    against the oracle's plain build (index work: exact, up to acceptance
+    tests that sit within rounding of the threshold)."""
+    from oracle import tree as otree
+    from tests.test_gpu_direct import _ragged
+    w = sph5120 if name == "sphere_5120" else _ragged()
+    s = _solver(w, leaf_panels=leaf, theta=theta)
+    t = s.tree()
+    v = w["verts"][w["tris"]]
+    cen = v.mean(axis=1)
+    bary = np.array([[2 / 3, 1 / 6, 1 / 6], [1 / 6, 2 / 3, 1 / 6], [1 / 6, 1 / 6, 2 / 3]])
+    nodes = np.einsum("qk,jkd->jqd", bary, v)
+    ob = otree.build(cen, nodes, leaf)
+    ol = otree.lists(ob, theta)
+    boxes, lists = _tree_sets(t)
+    osets = [frozenset(b["panels"]) for b in ob]
+    assert sorted(map(sorted, boxes)) == sorted(map(sorted, osets))
+    index = {b: i for i, b in enumerate(boxes)}
+    scale = np.abs(v).max()
+    for b, ps in zip(ob, osets):
+        i = index[ps]
+        assert t["box_level"][i] == b["level"]
+        assert np.abs(t["box_centre"][i] - b["centre"]).max() < 1e-13 * scale
+        assert abs(t["box_radius"][i][0] - b["R"]) < 1e-13 * scale
+        assert abs(t["box_radius"][i][1] - b["RT"]) < 1e-13 * scale
+    ties = 0
+    for tl, (om2p, op2p) in ol.items():
+        T = ob[tl]
+        m2p, p2p = lists[osets[tl]]
+        om2p = {osets[b] for b in om2p}
+        op2p = {osets[b] for b in op2p}
+        if (m2p, p2p) == (om2p, op2p):
+            continue
+        # a difference is allowed only where the acceptance test is a tie
+        for B in (m2p ^ om2p):
+            ob_B = ob[osets.index(B)]
+            sep = np.linalg.norm(ob_B["centre"] - T["centre"]) - T["RT"]
+            assert abs(ob_B["R"] - theta * sep) < 1e-12 * scale
+            ties += 1
+    assert ties <= 2
+    print(name, "boxes", len(boxes), "leaves", len(lists), "ties", ties)

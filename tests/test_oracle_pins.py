@@ -442,3 +442,59 @@ def test_bem_converges_to_kirkwood_cfg0():
     assert 3.5 < e0 / e1 < 4.5
     rich = vals[1] + (vals[1] - vals[0]) / 3.0
     assert abs(rich - ref) < 1e-4 * abs(ref)
+
+
+# ------------------------------------------------------- vacuum binding leg
+def test_vacuum_energy_closed_forms():
+    """eq. energy_multipole_polarizable in vacuum: two point charges give
+    C q1 q2 / r; a charge facing a neutral polarisable site (no damping)
+    gives the ion-induced-dipole energy -C alpha q^2 / (2 r^4), the
+    polarisation work being carried by the d-form of the energy."""
+    from oracle import solver as osolver, multipoles as omp
+    C = omp.COULOMB_KCAL
+    xyz = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 3.0]])
+    Z = np.zeros((2, 9))
+    d0 = np.zeros((2, 3))
+    q = np.array([0.7, -0.4])
+    G = osolver.vacuum_energy(xyz, q, d0, Z, np.zeros(2), np.zeros((2, 3)))
+    assert abs(G - C * 0.7 * -0.4 / 3.0) < 1e-12 * abs(G)
+    q = np.array([0.8, 0.0])
+    alpha = np.array([0.0, 1.3])
+    grp = np.arange(2)
+    mu, _, _ = osolver.scf(xyz, q, d0, Z, alpha, grp, 1.0, 1e30, 0.7, 1e-13, 1000)
+    assert abs(mu[1, 2] - 1.3 * 0.8 / 9.0) < 1e-13
+    G = osolver.vacuum_energy(xyz, q, d0, Z, alpha, mu, thole_a=1e30)
+    assert abs(G - (-C * 1.3 * 0.8 ** 2 / (2 * 3.0 ** 4))) < 1e-10 * abs(G)
+
+
+def test_vacuum_binding_vanishes_at_separation():
+    """G_AB - G_A - G_B tends to the monopole interaction of the two parts
+    as they move apart."""
+    from oracle import solver as osolver
+    rng = np.random.default_rng(4)
+    from synth.sites import sites_in_ball
+    from synth import random_multipoles
+    A = sites_in_ball(rng, 5, 2.0, 1.0)
+    B = sites_in_ball(rng, 4, 2.0, 1.0)
+    mA = random_multipoles(rng, 5)
+    mB = random_multipoles(rng, 4)
+
+    def G(xyz, m):
+        q, d, Q9, al = m
+        mu, _, _ = osolver.scf(xyz, q, d, Q9, al, np.arange(len(q)), 1.0, 0.39, 0.7, 1e-12, 2000)
+        return osolver.vacuum_energy(xyz, q, d, Q9, al, mu)
+
+    gA, gB = G(A, mA), G(B, mB)
+    vals = []
+    for sep in (10.0, 100.0, 1000.0):
+        xyz = np.concatenate([A, B + [sep, 0, 0]])
+        m = tuple(np.concatenate([a, b]) for a, b in zip(mA, mB))
+        vals.append(G(xyz, m) - gA - gB)
+    qA, qB = mA[0].sum(), mB[0].sum()
+    from oracle import multipoles as omp
+    lead = omp.COULOMB_KCAL * qA * qB
+    # the binding energy approaches the monopole term C qA qB / sep, the
+    # remainder falling as 1/sep^2 (charge-dipole order)
+    e = [abs(v - lead / s) for v, s in zip(vals, (10.0, 100.0, 1000.0))]
+    assert e[2] < 1e-2 * abs(lead / 1000.0)
+    assert 50 < e[1] / e[2] < 200
