@@ -64,11 +64,49 @@ def cpu_baseline(w, target_seconds):
     dt = time.perf_counter() - t0
     pairs = rows * N * 3.0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    one = _one_core_rate(w, max(1.0, target_seconds / 4))
     return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": cores,
             "kind": "oracle",
             "sample": "FP64 oracle direct operator sums (all four kernels, "
                       "near/self rules included) for target rows 0..%d of the "
-                      "%d-panel workload: %.3e pairs in %.1f s" % (rows, N, pairs, dt)}
+                      "%d-panel workload: %.3e pairs in %.1f s" % (rows, N, pairs, dt),
+            "one_core_value": one}
+
+
+_ONE_CORE = """
+import sys, time, numpy as np
+sys.path.insert(0, sys.argv[1])
+from oracle import bie
+z = np.load(sys.argv[2])
+m = bie.Mesh(z["verts"], z["tris"], float(z["kappa"]))
+x = np.random.default_rng(0).normal(size=2 * m.N)
+rows, dt = 8, 0.0
+while dt < float(sys.argv[3]) and rows < m.N:
+    rows = min(m.N, rows * 4)
+    t0 = time.perf_counter()
+    m.operator_sums(x[:m.N], x[m.N:], rows=(0, rows))
+    dt = time.perf_counter() - t0
+print(rows * m.N * 3.0 / dt)
+"""
+
+
+def _one_core_rate(w, seconds):
+    """The same oracle sums on one thread (a child process with
+    OMP_NUM_THREADS=1), pair-interactions per second."""
+    import subprocess
+    import tempfile
+    import numpy as np
+    root = os.path.dirname(os.path.abspath(__file__))
+    with tempfile.TemporaryDirectory() as d:
+        f = os.path.join(d, "mesh.npz")
+        np.savez(f, verts=w["verts"], tris=w["tris"], kappa=w["params"]["kappa"])
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-c", _ONE_CORE, root, f, str(seconds)],
+                           env=env, capture_output=True, text=True, timeout=600)
+    try:
+        return float(r.stdout.strip().splitlines()[-1])
+    except (ValueError, IndexError):
+        return None
 
 
 def main():

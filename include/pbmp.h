@@ -209,6 +209,23 @@ typedef struct pbmp_kstats {
 } pbmp_kstats;
 int pbmp_kernel_stats(pbmp_ctx *c, int mode, pbmp_kstats *out);
 
+/* Ion-exclusion (Stern) layer (section "Spherical cavity": the verification
+ * case surrounds the cavity by a 1 A layer): an outer closed surface
+ * enclosing the mesh of pbmp_set_mesh, same layout and checks as there.
+ * Regions: inside the mesh eps_in (the sites), between the two surfaces
+ * eps_stern without ions, outside the outer surface eps_out and kappa.  The
+ * solve then works on both surfaces' densities (the one-surface system of
+ * each surface coupled by the layer potentials of the other at its
+ * collocation points; the reaction field comes from the inner surface);
+ * pbmp_matvec applies that coupled operator to [phi1, dphi1, phi2, dphi2]
+ * ([2 nt1 + 2 nt2], caller's panel order within each surface).  Call after
+ * pbmp_set_mesh; nt = 0 removes the layer.  Direct mode only (PBMP_EARG in
+ * treecode mode); pbmp_backward and transposed products are not available
+ * with a layer (PBMP_ESTATE).  PBMP_EMESH when the outer surface does not
+ * enclose the inner one. */
+int pbmp_set_stern(pbmp_ctx *c, int64_t nv, const double *verts, int64_t nt,
+                   const int32_t *tris, double eps_stern, int where);
+
 /* The octree and interaction lists that pbmp_set_mesh built in treecode
  * mode (section "The treecode algorithm"; panels binned by centroid on a
  * 2^21 grid over the bounding cube, a cell split while it holds more than

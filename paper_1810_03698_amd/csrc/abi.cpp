@@ -143,6 +143,14 @@ int pbmp_kernel_stats(pbmp_ctx *c, int mode, pbmp_kstats *out) {
   });
 }
 
+int pbmp_set_stern(pbmp_ctx *c, int64_t nv, const double *verts, int64_t nt,
+                   const int32_t *tris, double eps_stern, int where) {
+  return guarded(c, [&] {
+    c->rt->set_stern(nv, verts, nt, tris, eps_stern, where);
+    return 0;
+  });
+}
+
 int pbmp_tree_export(pbmp_ctx *c, int64_t counts[4], int32_t *perm, int32_t *box_range,
                      int32_t *box_level, double *box_centre, double *box_radius,
                      int32_t *leaf_box, int32_t *m2p_ptr, int32_t *m2p_box,

@@ -59,10 +59,17 @@ void launch_mesh_adjoint(hipStream_t s, int N, int M, int nf, const double *src6
                          const double *p, const double *Q, const double *Wp, double kappa,
                          double eps_ratio, double *work, double *ge, double *out);
 
-void Runtime::apply_transpose(const double *x, double *y) {
-  launch_transpose(s_, fp64(), ru_.nf, N_, src64_.p, src32_.p, geo_.p, tgt32_.p, x, o.kappa,
-                   p2p_chunks_, part_.p, trow_.p, tcol_.p, tent_.p, nval_.p,
-                   o.eps_in / o.eps_out, y);
+void Runtime::apply_transpose(const double *x, double *y, bool f64) {
+  const bool use64 = f64 || fp64();
+  const double *val = (use64 && !fp64()) ? nval64_.p : nval_.p;
+  if (use_tree())
+    tree_apply_transpose(*tree_, s_, use64, ru_.nf, N_, geo_.p, src64_.p, src32_.p, tgt32_.p,
+                         x, o.kappa, part_.p, trow_.p, tcol_.p, tent_.p, val,
+                         o.eps_in / o.eps_out, y);
+  else
+    launch_transpose(s_, use64, ru_.nf, N_, src64_.p, src32_.p, geo_.p, tgt32_.p, x, o.kappa,
+                     p2p_chunks_, part_.p, trow_.p, tcol_.p, tent_.p, val,
+                     o.eps_in / o.eps_out, y);
   ++matvecs_;
 }
 
@@ -73,6 +80,7 @@ void Runtime::precond_T(const double *u, double *z) {
 int Runtime::backward(double dGbar, double *g_xyz, double *g_q, double *g_d, double *g_Q,
                       double *g_verts, int where) {
   PBMP_REQUIRE(solved_, PBMP_ESTATE, "backward needs a completed solve on this context");
+  PBMP_REQUIRE(!outer_, PBMP_ESTATE, "backward is not available with a Stern layer");
   PBMP_REQUIRE(where == PBMP_HOST || where == PBMP_DEVICE, PBMP_EARG, "bad where");
   const int M = M_, N = N_;
   const double c = dGbar * coulomb_kcal() * 0.5;

@@ -187,4 +187,20 @@ void launch_permute(hipStream_t s, int n, int blocks, const int *perm,
   PBMP_HIP(hipGetLastError());
 }
 
+namespace {
+__global__ void k_add_strided(int n, double sign, const double *__restrict__ p, int stride,
+                              double *__restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += sign * p[(size_t)stride * i];
+}
+}  // namespace
+
+// y[i] += sign * p[stride * i]
+void launch_add_strided(hipStream_t s, int n, double sign, const double *p, int stride,
+                        double *y) {
+  hipLaunchKernelGGL(k_add_strided, dim3((n + 255) / 256), dim3(256), 0, s, n, sign, p, stride,
+                     y);
+  PBMP_HIP(hipGetLastError());
+}
+
 }  // namespace pbmp

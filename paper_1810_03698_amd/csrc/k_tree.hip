@@ -61,6 +61,8 @@ template <int P> struct Multi {
   }
 };
 
+constexpr double kInv4PiT = 0.07957747154594767;
+
 // binomial coefficients C(a, b), a, b <= 6
 __constant__ double kBinom[7][7] = {
     {1, 0, 0, 0, 0, 0, 0},   {1, 1, 0, 0, 0, 0, 0},    {1, 2, 1, 0, 0, 0, 0},
@@ -210,8 +212,20 @@ __global__ void k_cast(size_t n, const double *__restrict__ a, float *__restrict
 // G and TPT are chosen per task to use the most lanes.  The LDS tile is
 // small and the groups' sums meet through lane shuffles, so a task holds
 // 2 KB of LDS and many waves fit on a CU.
-constexpr int kTileT = 32;
-constexpr int kMaxTPT = 3;
+#ifndef PBMP_P2P_TILE
+#define PBMP_P2P_TILE 128
+#endif
+#ifndef PBMP_P2P_MAXTPT
+#define PBMP_P2P_MAXTPT 5
+#endif
+#ifndef PBMP_P2P_GROUPS
+#define PBMP_P2P_GROUPS 1
+#endif
+#ifndef PBMP_M2P_GROUPS
+#define PBMP_M2P_GROUPS 1
+#endif
+constexpr int kTileT = PBMP_P2P_TILE;
+constexpr int kMaxTPT = PBMP_P2P_MAXTPT;
 
 struct LaneSplit {
   int G, L, tpt;
@@ -223,7 +237,7 @@ struct LaneSplit {
 __device__ inline LaneSplit lane_split(int nt) {
   LaneSplit best{1, 64, min(kMaxTPT, (nt + 63) / 64)};
   float be = (float)nt / (64.0f * best.tpt * ((nt + 64 * best.tpt - 1) / (64 * best.tpt)));
-  for (int G = 2; G <= 16; ++G) {
+  for (int G = 2; G <= 16 * PBMP_P2P_GROUPS; ++G) {
     const int L = 64 / G;
     const int tpt = (nt + L - 1) / L;
     if (tpt > kMaxTPT) continue;
@@ -354,7 +368,13 @@ __global__ __launch_bounds__(64) void k_p2p_tasks(int ntask, const int *__restri
                                  sh, ls.G, ls.L)
     case 1: PBMP_BODY(1); break;
     case 2: PBMP_BODY(2); break;
+#if PBMP_P2P_MAXTPT >= 4
+    case 3: PBMP_BODY(3); break;
+    case 4: PBMP_BODY(4); break;
+    default: PBMP_BODY(kMaxTPT); break;
+#else
     default: PBMP_BODY(3); break;
+#endif
 #undef PBMP_BODY
   }
 }
@@ -402,7 +422,7 @@ __global__ __launch_bounds__(64) void k_m2p_tasks(int ntask, const int *__restri
   int G = 1;
   {
     float be = 0.0f;
-    for (int g = 1; g <= 16; ++g) {
+    for (int g = 1; g <= 16 * PBMP_M2P_GROUPS; ++g) {
       const int L = 64 / g;
       const float e = (float)nt * nb / (64.0f * ((nt + L - 1) / L) * ((nb + g - 1) / g));
       if (e > be) {
@@ -545,6 +565,403 @@ void launch_moments(Tree &t, hipStream_t s, int nf, const double *src64) {
   }
 }
 
+
+// ===================================================== transposed product
+// A^T z for the adjoint solve, the exact transpose of the treecode product
+// above: P2P^T runs the forward P2P pairs with sources on lanes; M2P^T
+// gathers, for every accepted box B, local coefficients
+//   L_B,k = sum over the targets i of the leaves that accepted B of z_i a_k(x_i - c_B)
+// (Laplace coefficients with the first component of z, Yukawa with the
+// second); L2L shifts them down the tree, (h + t)^k expanded as in M2M with
+// the roles transposed; L2P evaluates at every node y, h = y - c_leaf,
+//   V^T: sum_k L_k h^k,   K^T: n . grad_h sum_k L_k h^k.
+
+template <class T, int NF, int SPT>
+__device__ void p2pT_body(const T *__restrict__ src, const T *__restrict__ tgt,
+                          const double *__restrict__ z, const double *__restrict__ geo, int N,
+                          int s0, int s1, const int *__restrict__ ranges, int lb, int le,
+                          T kappa, T nk, int slot, double *__restrict__ part, T *sh, int G,
+                          int L) {
+  const int lane = (int)threadIdx.x;
+  const int gi = lane / L, li = lane - gi * L;
+  const bool active = gi < G;
+  for (int sb = s0; sb < s1; sb += L * SPT) {
+    T rec[SPT][16];
+    int sj[SPT];
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+      sj[k] = sb + k * L + li;
+      const int jl = min(sj[k], s1 - 1);
+      for (int c = 0; c < 16; ++c) rec[k][c] = src[16 * (size_t)jl + c];
+    }
+    double S[SPT][4];
+#pragma unroll
+    for (int k = 0; k < SPT; ++k)
+      for (int c = 0; c < 4; ++c) S[k][c] = 0.0;
+    for (int l = lb; l < le; ++l) {
+      const int a0 = ranges[2 * l], a1 = ranges[2 * l + 1];
+      for (int it = a0; it < a1; it += 64) {
+        const int nt = min(64, a1 - it);
+        __syncthreads();
+        if (lane < nt) {
+          const int i = it + lane;
+          sh[5 * lane] = tgt[i];
+          sh[5 * lane + 1] = tgt[N + i];
+          sh[5 * lane + 2] = tgt[2 * N + i];
+          sh[5 * lane + 3] = (T)z[i];
+          sh[5 * lane + 4] = (T)z[N + i];
+        }
+        __syncthreads();
+        T a[SPT][4];
+#pragma unroll
+        for (int k = 0; k < SPT; ++k)
+          for (int c = 0; c < 4; ++c) a[k][c] = T(0);
+        for (int e = active ? gi : nt; e < nt; e += G) {
+          const T *r = sh + 5 * e;
+#pragma unroll
+          for (int k = 0; k < SPT; ++k) {
+            T t4[4];
+            panel_terms<T>(rec[k], NF, r[0], r[1], r[2], kappa, nk, t4);
+            a[k][0] += r[3] * t4[0];
+            a[k][1] += r[3] * t4[1];
+            a[k][2] += r[4] * t4[2];
+            a[k][3] += r[4] * t4[3];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < SPT; ++k)
+          for (int c = 0; c < 4; ++c) S[k][c] += (double)a[k][c];
+      }
+    }
+    if (G > 1) {
+#pragma unroll
+      for (int k = 0; k < SPT; ++k)
+        for (int c = 0; c < 4; ++c) {
+          const double v = S[k][c];
+          double acc = v;
+          for (int g = 1; g < G; ++g) acc += __shfl(v, li + g * L, 64);
+          S[k][c] = acc;
+        }
+    }
+    if (gi == 0)
+#pragma unroll
+      for (int k = 0; k < SPT; ++k)
+        if (sj[k] < s1) {
+          const double wA = geo[6 * (size_t)N + sj[k]] * kInv4PiT / NF;
+          for (int c = 0; c < 4; ++c) part[((size_t)slot * 4 + c) * N + sj[k]] = wA * S[k][c];
+        }
+  }
+}
+
+template <class T, int NF>
+__global__ __launch_bounds__(64) void k_p2pT_tasks(int ntask, const int *__restrict__ tasks,
+                                                   const int *__restrict__ range,
+                                                   const int *__restrict__ subs,
+                                                   const T *__restrict__ src,
+                                                   const T *__restrict__ tgt,
+                                                   const double *__restrict__ z,
+                                                   const double *__restrict__ geo, int N,
+                                                   T kappa, T nk, double *__restrict__ part) {
+  __shared__ T sh[64 * 5];
+  const int task = xcd_task(ntask);
+  if (task < 0) return;
+  const int B = tasks[4 * task], lb = tasks[4 * task + 1], le = tasks[4 * task + 2];
+  const int slot = tasks[4 * task + 3];
+  const int s0 = range[2 * B], s1 = range[2 * B + 1];
+  // split for the sources (at most two panels per lane: records stay in registers)
+  const int ns = s1 - s0;
+  int G = 1, spt = min(2, (ns + 63) / 64);
+  float be = (float)ns / (64.0f * spt * ((ns + 64 * spt - 1) / (64 * spt)));
+  for (int g = 2; g <= 16; ++g) {
+    const int L = 64 / g, tp = (ns + L - 1) / L;
+    if (tp > 2) continue;
+    const float e = (float)(g * ns) / (64.0f * tp);
+    if (e > be) {
+      be = e;
+      G = g;
+      spt = tp;
+    }
+  }
+  if (spt == 1)
+    p2pT_body<T, NF, 1>(src, tgt, z, geo, N, s0, s1, subs, lb, le, kappa, nk, slot, part, sh,
+                        G, 64 / G);
+  else
+    p2pT_body<T, NF, 2>(src, tgt, z, geo, N, s0, s1, subs, lb, le, kappa, nk, slot, part, sh,
+                        G, 64 / G);
+}
+
+// M2P^T: per task (box B, target sub-ranges) the partial local coefficients
+// of one kernel family (YUK: Yukawa with z2, else Laplace with z1)
+template <class T, int P, bool YUK>
+__global__ __launch_bounds__(64) void k_m2pT_tasks(int ntask, const int *__restrict__ tasks,
+                                                   const int *__restrict__ subs,
+                                                   const double *__restrict__ center,
+                                                   const T *__restrict__ tgt,
+                                                   const double *__restrict__ z, int N,
+                                                   T kappa, T nk, double *__restrict__ Lpart) {
+  constexpr Multi<P> mi{};
+  constexpr int NC = Multi<P>::n;
+  const int task = xcd_task(ntask);
+  if (task < 0) return;
+  const int B = tasks[4 * task], lb = tasks[4 * task + 1], le = tasks[4 * task + 2];
+  const T cx = (T)center[3 * B], cy = (T)center[3 * B + 1], cz = (T)center[3 * B + 2];
+  T acc[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) acc[k] = T(0);
+  for (int l = lb; l < le; ++l) {
+    const int a0 = subs[2 * l], a1 = subs[2 * l + 1];
+    for (int t = a0 + (int)threadIdx.x; t < a1; t += 64) {
+      const T D[3] = {tgt[t] - cx, tgt[N + t] - cy, tgt[2 * N + t] - cz};
+      const T R2 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
+      const T ri = rsqrt_t<T>(R2);
+      const T iR2 = ri * ri;
+      if (!YUK) {
+        const T w = (T)z[t];
+        T a[NC];
+        a[0] = ri;
+#pragma unroll
+        for (int k = 1; k < NC; ++k) {
+          const int s = mi.deg[k];
+          T S1 = T(0), S2 = T(0);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            if (mi.m1[k][d] >= 0) S1 += D[d] * a[mi.m1[k][d]];
+            if (mi.m2[k][d] >= 0) S2 += a[mi.m2[k][d]];
+          }
+          a[k] = (T(2 * s - 1) / T(s) * S1 - T(s - 1) / T(s) * S2) * iR2;
+        }
+#pragma unroll
+        for (int k = 0; k < NC; ++k) acc[k] += w * a[k];
+      } else {
+        const T w = (T)z[N + t];
+        const T ek = expneg_t<T>(nk, kappa, R2 * ri);
+        T ay[NC], by[NC];
+        by[0] = ek;
+        ay[0] = ek * ri;
+#pragma unroll
+        for (int k = 1; k < NC; ++k) {
+          const int s = mi.deg[k];
+          T Y1 = T(0), Y2 = T(0), B1 = T(0), B2 = T(0);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            if (mi.m1[k][d] >= 0) {
+              Y1 += D[d] * ay[mi.m1[k][d]];
+              B1 += D[d] * by[mi.m1[k][d]];
+            }
+            if (mi.m2[k][d] >= 0) {
+              Y2 += ay[mi.m2[k][d]];
+              B2 += by[mi.m2[k][d]];
+            }
+          }
+          const T ks = kappa / T(s);
+          by[k] = ks * (Y1 - Y2);
+          ay[k] = (T(2 * s - 1) / T(s) * Y1 - T(s - 1) / T(s) * Y2 + ks * (B1 - B2)) * iR2;
+        }
+#pragma unroll
+        for (int k = 0; k < NC; ++k) acc[k] += w * ay[k];
+      }
+    }
+  }
+  // wave sums in FP64, lane 0 writes
+  double *out = Lpart + (size_t)task * 2 * NC + (YUK ? NC : 0);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    double v = (double)acc[k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (threadIdx.x == 0) out[k] = v;
+  }
+}
+
+// L_B = sum of the partials of B's tasks (fixed order); zero without tasks
+__global__ void k_l_reduce(int nbox, int ncoef2, const int *__restrict__ count,
+                           const int *__restrict__ off, const double *__restrict__ Lpart,
+                           double *__restrict__ Lb) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nbox * ncoef2) return;
+  const int B = e / ncoef2, k = e % ncoef2;
+  double v = 0.0;
+  const int t0 = off[B], nt = count[2 * B + 1];
+  for (int t = t0; t < t0 + nt; ++t) v += Lpart[(size_t)t * ncoef2 + k];
+  Lb[e] = v;
+}
+
+// L2L for the boxes of one level: each child adds its parent's expansion
+// re-centred, L_C,j += sum_{k >= j} C(k, j) t^{k-j} L_B,k, t = c_C - c_B
+template <int P>
+__global__ __launch_bounds__(64) void k_l2l(int base, const int *__restrict__ child,
+                                            const double *__restrict__ center,
+                                            double *__restrict__ Lb) {
+  constexpr Multi<P> mi{};
+  constexpr int NC = Multi<P>::n;
+  __shared__ double tp[3][P + 1];
+  __shared__ double lp[2 * NC];
+  const int B = base + (int)blockIdx.x;
+  if (child[8 * B] < 0) return;  // a leaf (uniform per block)
+  for (int k = threadIdx.x; k < 2 * NC; k += 64) lp[k] = Lb[(size_t)B * 2 * NC + k];
+  for (int cc = 0; cc < 8; ++cc) {
+    const int C = child[8 * B + cc];
+    if (C < 0) break;
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      const double t = center[3 * C + threadIdx.x] - center[3 * B + threadIdx.x];
+      double p = 1.0;
+      for (int e = 0; e <= P; ++e) {
+        tp[threadIdx.x][e] = p;
+        p *= t;
+      }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < NC; j += 64) {
+      const int jx = mi.e[j][0], jy = mi.e[j][1], jz = mi.e[j][2];
+      double vl = 0.0, vy = 0.0;
+      for (int kx = jx; kx <= P; ++kx)
+        for (int ky = jy; kx + ky <= P; ++ky)
+          for (int kz = jz; kx + ky + kz <= P; ++kz) {
+            const int k = Multi<P>::index(kx, ky, kz);
+            const double w = kBinom[kx][jx] * tp[0][kx - jx] * kBinom[ky][jy] *
+                             tp[1][ky - jy] * kBinom[kz][jz] * tp[2][kz - jz];
+            vl += w * lp[k];
+            vy += w * lp[NC + k];
+          }
+      Lb[(size_t)C * 2 * NC + j] += vl;
+      Lb[(size_t)C * 2 * NC + NC + j] += vy;
+    }
+  }
+}
+
+// L2P at the leaves: lanes over the leaf's panels, FP64
+template <int P, int NF>
+__global__ __launch_bounds__(64) void k_l2p(const int *__restrict__ leaves,
+                                            const int *__restrict__ range,
+                                            const double *__restrict__ center,
+                                            const double *__restrict__ Lb,
+                                            const double *__restrict__ src64,
+                                            const double *__restrict__ geo,
+                                            const int *__restrict__ tslotsT, int N,
+                                            double *__restrict__ part) {
+  constexpr Multi<P> mi{};
+  constexpr int NC = Multi<P>::n;
+  __shared__ double lp[2 * NC];
+  const int B = leaves[blockIdx.x];
+  for (int k = threadIdx.x; k < 2 * NC; k += 64) lp[k] = Lb[(size_t)B * 2 * NC + k];
+  __syncthreads();
+  const double c[3] = {center[3 * B], center[3 * B + 1], center[3 * B + 2]};
+  for (int j = range[2 * B] + (int)threadIdx.x; j < range[2 * B + 1]; j += 64) {
+    const double *r = src64 + 16 * (size_t)j;
+    const double n[3] = {r[9], r[10], r[11]};
+    double out[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < NF; ++q) {
+      const double h[3] = {r[3 * q] - c[0], r[3 * q + 1] - c[1], r[3 * q + 2] - c[2]};
+      double mono[NC];
+      mono[0] = 1.0;
+#pragma unroll
+      for (int k = 1; k < NC; ++k) {
+        const int d = mi.e[k][0] ? 0 : (mi.e[k][1] ? 1 : 2);
+        mono[k] = mono[mi.m1[k][d]] * h[d];
+      }
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        double dn = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          if (mi.m1[k][d] >= 0) dn += mi.e[k][d] * n[d] * mono[mi.m1[k][d]];
+        out[0] += lp[k] * mono[k];
+        out[1] += lp[k] * dn;
+        out[2] += lp[NC + k] * mono[k];
+        out[3] += lp[NC + k] * dn;
+      }
+    }
+    const double wA = geo[6 * (size_t)N + j] * kInv4PiT / NF;
+    const int slot = tslotsT[j] - 1;
+    for (int k = 0; k < 4; ++k) part[((size_t)slot * 4 + k) * N + j] = wA * out[k];
+  }
+}
+
+// (A^T z) from the transposed partial slots, the transposed near/self
+// correction and the identity terms
+__global__ void k_finish_T_slots(int N, const int *__restrict__ tslotsT,
+                                 const double *__restrict__ part, const int *__restrict__ trow,
+                                 const int *__restrict__ tcol, const int *__restrict__ tent,
+                                 const double *__restrict__ val, const double *__restrict__ z,
+                                 double eps_ratio, double *__restrict__ y) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  double S[4] = {0.0, 0.0, 0.0, 0.0};
+  const int ns = tslotsT[j];
+  for (int c = 0; c < ns; ++c)
+    for (int k = 0; k < 4; ++k) S[k] += part[((size_t)c * 4 + k) * N + j];
+  for (int t = trow[j]; t < trow[j + 1]; ++t) {
+    const int i = tcol[t];
+    const size_t e = tent[t];
+    S[0] += val[4 * e] * z[i];
+    S[1] += val[4 * e + 1] * z[i];
+    S[2] += val[4 * e + 2] * z[N + i];
+    S[3] += val[4 * e + 3] * z[N + i];
+  }
+  y[j] = 0.5 * z[j] + S[1] + 0.5 * z[N + j] - S[3];
+  y[N + j] = -S[0] + eps_ratio * S[2];
+}
+
+template <class T, int P>
+void tree_T_far(Tree &t, hipStream_t s, int nf, int N, const double *geo,
+                const double *src64, const T *src, const T *tgt, const double *z, T kappa,
+                T nk, double *part) {
+  constexpr int NC = Multi<P>::n;
+  // P2P^T
+  const int nbp = ((t.n_p2pT_tasks + 7) / 8) * 8;
+  if (nf == 3)
+    hipLaunchKernelGGL((k_p2pT_tasks<T, 3>), dim3(nbp), dim3(64), 0, s, t.n_p2pT_tasks,
+                       t.d_p2pT_task.p, t.d_range.p, t.d_p2pT_sub.p, src, tgt, z, geo, N,
+                       kappa, nk, part);
+  else
+    hipLaunchKernelGGL((k_p2pT_tasks<T, 1>), dim3(nbp), dim3(64), 0, s, t.n_p2pT_tasks,
+                       t.d_p2pT_task.p, t.d_range.p, t.d_p2pT_sub.p, src, tgt, z, geo, N,
+                       kappa, nk, part);
+  // M2P^T, per-box sums, L2L down the levels, L2P at the leaves
+  t.d_Lpart.reserve((size_t)std::max(1, t.n_m2pT_tasks) * 2 * NC);
+  t.d_L.reserve((size_t)t.nbox * 2 * NC);
+  if (t.n_m2pT_tasks > 0) {
+    const int nbm = ((t.n_m2pT_tasks + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_m2pT_tasks<T, P, false>), dim3(nbm), dim3(64), 0, s,
+                       t.n_m2pT_tasks, t.d_m2pT_task.p, t.d_m2pT_sub.p, t.d_center.p, tgt, z,
+                       N, kappa, nk, t.d_Lpart.p);
+    hipLaunchKernelGGL((k_m2pT_tasks<T, P, true>), dim3(nbm), dim3(64), 0, s,
+                       t.n_m2pT_tasks, t.d_m2pT_task.p, t.d_m2pT_sub.p, t.d_center.p, tgt, z,
+                       N, kappa, nk, t.d_Lpart.p);
+  }
+  const int nl = t.nbox * 2 * NC;
+  hipLaunchKernelGGL(k_l_reduce, dim3((nl + 255) / 256), dim3(256), 0, s, t.nbox, 2 * NC,
+                     t.d_m2pT_count.p, t.d_m2pT_off.p, t.d_Lpart.p, t.d_L.p);
+  for (int l = 0; l < t.depth; ++l) {
+    const int nb = t.level_start[l + 1] - t.level_start[l];
+    if (nb > 0)
+      hipLaunchKernelGGL(k_l2l<P>, dim3(nb), dim3(64), 0, s, t.level_start[l], t.d_child.p,
+                         t.d_center.p, t.d_L.p);
+  }
+  if (nf == 3)
+    hipLaunchKernelGGL((k_l2p<P, 3>), dim3(t.nleaf), dim3(64), 0, s, t.d_leaves.p,
+                       t.d_range.p, t.d_center.p, t.d_L.p, src64, geo, t.d_tslotsT.p, N, part);
+  else
+    hipLaunchKernelGGL((k_l2p<P, 1>), dim3(t.nleaf), dim3(64), 0, s, t.d_leaves.p,
+                       t.d_range.p, t.d_center.p, t.d_L.p, src64, geo, t.d_tslotsT.p, N, part);
+  PBMP_HIP(hipGetLastError());
+}
+
+template <class T>
+void tree_T_far_p(Tree &t, hipStream_t s, int nf, int N, const double *geo,
+                  const double *src64, const T *src, const T *tgt, const double *z, T kappa,
+                  T nk, double *part) {
+  switch (t.prm.order) {
+    case 1: tree_T_far<T, 1>(t, s, nf, N, geo, src64, src, tgt, z, kappa, nk, part); break;
+    case 2: tree_T_far<T, 2>(t, s, nf, N, geo, src64, src, tgt, z, kappa, nk, part); break;
+    case 3: tree_T_far<T, 3>(t, s, nf, N, geo, src64, src, tgt, z, kappa, nk, part); break;
+    case 4: tree_T_far<T, 4>(t, s, nf, N, geo, src64, src, tgt, z, kappa, nk, part); break;
+    case 5: tree_T_far<T, 5>(t, s, nf, N, geo, src64, src, tgt, z, kappa, nk, part); break;
+    case 6: tree_T_far<T, 6>(t, s, nf, N, geo, src64, src, tgt, z, kappa, nk, part); break;
+    default: throw Error(PBMP_EARG, "treecode order must be 1..6");
+  }
+}
+
 }  // namespace
 
 void tree_upload_exponents(Tree &t, hipStream_t s) {
@@ -606,6 +1023,21 @@ void launch_finish_slots(hipStream_t s, int N, const int *tslots, const double *
                          const double *x, double eps_ratio, double *y) {
   hipLaunchKernelGGL(k_finish_slots, dim3((N + 255) / 256), dim3(256), 0, s, N, tslots,
                      part, rowptr, col, val, x, eps_ratio, y);
+  PBMP_HIP(hipGetLastError());
+}
+
+void tree_apply_transpose(Tree &t, hipStream_t s, bool fp64, int nf, int N, const double *geo,
+                          const double *src64, const float *src32, const float *tgt32,
+                          const double *z, double kappa, double *part, const int *trow,
+                          const int *tcol, const int *tent, const double *val, double eps_ratio,
+                          double *y) {
+  if (fp64)
+    tree_T_far_p<double>(t, s, nf, N, geo, src64, src64, geo, z, kappa, 0.0, part);
+  else
+    tree_T_far_p<float>(t, s, nf, N, geo, src64, src32, tgt32, z, (float)kappa,
+                        (float)(-kappa * 1.4426950408889634), part);
+  hipLaunchKernelGGL(k_finish_T_slots, dim3((N + 255) / 256), dim3(256), 0, s, N,
+                     t.d_tslotsT.p, part, trow, tcol, tent, val, z, eps_ratio, y);
   PBMP_HIP(hipGetLastError());
 }
 

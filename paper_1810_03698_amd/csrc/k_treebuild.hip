@@ -355,10 +355,112 @@ __global__ void k_column(int n, const int *__restrict__ count, int c, int *__res
   if (i < n) out[i] = count[8 * (size_t)i + c];
 }
 
+__global__ void k_column2(int n, const int *__restrict__ count, int c, int *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = count[2 * (size_t)i + c];
+}
+
 __global__ void k_target_slots(int N, const int *__restrict__ owner,
                                const int *__restrict__ slots_of_box, int *__restrict__ tsl) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < N) tsl[i] = slots_of_box[owner[i]];
+}
+
+
+// ---- transposed lists (for the adjoint product) -------------------------
+// entries of a per-leaf CSR list as (box, leaf index) pairs
+__global__ void k_expand_pairs(int nleaf, const int *__restrict__ ptr,
+                               const int *__restrict__ box, int *__restrict__ key,
+                               int *__restrict__ val) {
+  const int li = blockIdx.x * blockDim.x + threadIdx.x;
+  if (li >= nleaf) return;
+  for (int e = ptr[li]; e < ptr[li + 1]; ++e) {
+    key[e] = box[e];
+    val[e] = li;
+  }
+}
+
+// CSR over boxes from pairs sorted by box: [first[b], last[b])
+__global__ void k_runs(int n, const int *__restrict__ key, int *__restrict__ first,
+                       int *__restrict__ last) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  if (e == 0 || key[e] != key[e - 1]) first[key[e]] = e;
+  if (e == n - 1 || key[e] != key[e + 1]) last[key[e]] = e + 1;
+}
+
+__global__ void k_fill_int(int n, int v, int *__restrict__ a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// Tasks of the transposed products.  For every box B (one thread), its
+// transposed list (the target leaves that hold B, in leaf order) is cut into
+// chunks of at most `chunk` target panels, stored as target sub-ranges.
+// count[b] = (sub-ranges, tasks); the filling pass writes
+// task = (box, sub begin, sub end, slot) and the sub-ranges.
+template <bool FILL>
+__global__ void k_tasks_T(int nbox, const int *__restrict__ first, const int *__restrict__ last,
+                          const int *__restrict__ val, const int *__restrict__ leaves, Boxes b,
+                          int chunk, int *__restrict__ count, const int *__restrict__ off_sub,
+                          const int *__restrict__ off_task, int *__restrict__ sub,
+                          int *__restrict__ task) {
+  const int B = blockIdx.x * blockDim.x + threadIdx.x;
+  if (B >= nbox) return;
+  int nsub = 0, ntask = 0, cnt = 0, os = 0, ot = 0, firstsub = 0;
+  if (FILL) {
+    os = off_sub[B];
+    ot = off_task[B];
+    firstsub = os;
+  }
+  for (int e = first[B]; e < last[B]; ++e) {
+    const int T = leaves[val[e]];
+    int s0 = b.start[T];
+    const int s1 = b.end[T];
+    while (s0 < s1) {
+      const int take = min(s1 - s0, chunk - cnt);
+      if (FILL) {
+        sub[2 * (os + nsub)] = s0;
+        sub[2 * (os + nsub) + 1] = s0 + take;
+      }
+      ++nsub;
+      s0 += take;
+      cnt += take;
+      if (cnt == chunk) {
+        if (FILL) {
+          int *tk = task + 4 * (ot + ntask);
+          tk[0] = B;
+          tk[1] = firstsub;
+          tk[2] = os + nsub;
+          tk[3] = ntask;
+          firstsub = os + nsub;
+        }
+        ++ntask;
+        cnt = 0;
+      }
+    }
+  }
+  if (cnt > 0) {
+    if (FILL) {
+      int *tk = task + 4 * (ot + ntask);
+      tk[0] = B;
+      tk[1] = firstsub;
+      tk[2] = os + nsub;
+      tk[3] = ntask;
+    }
+    ++ntask;
+  }
+  if (!FILL) {
+    count[2 * B] = nsub;
+    count[2 * B + 1] = ntask;
+  }
+}
+
+// per panel: number of transposed slots of its leaf (P2P^T tasks + 1)
+__global__ void k_source_slots(int N, const int *__restrict__ owner,
+                               const int *__restrict__ count, int *__restrict__ tsl) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) tsl[i] = count[2 * owner[i] + 1] + 1;
 }
 
 inline dim3 grid_for(size_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
@@ -406,6 +508,7 @@ void morton_order_device(hipStream_t s, int N, const double *verts, const int *t
 
 void Tree::build_device(int N, int nf, const uint64_t *key, const double *geo,
                         const double *src64, hipStream_t s) {
+  stream_ = s;
   ncoef = (prm.order + 1) * (prm.order + 2) * (prm.order + 3) / 6;
   Dbuf<int> owner, flag, idx;
   Dbuf<char> tmp;
@@ -534,6 +637,9 @@ void Tree::build_device(int N, int nf, const uint64_t *key, const double *geo,
                           hipMemcpyDeviceToDevice, s));
   PBMP_HIP(hipMemcpyAsync(d_p2p_ptr.p, off[1].p, sizeof(int) * (nleaf + 1),
                           hipMemcpyDeviceToDevice, s));
+  // transposed lists and tasks (adjoint product): P2P^T per source leaf,
+  // M2P^T per accepted box
+  build_transposed(N, owner.p, tmp);
   // per-product work counts and the largest slot count (host bookkeeping
   // for launches and counters)
   std::vector<int> h(8 * (size_t)nleaf);
@@ -551,6 +657,72 @@ void Tree::build_device(int N, int nf, const uint64_t *key, const double *geo,
   d_mom32.alloc((size_t)nbox * 2 * ncoef);
   tree_upload_exponents(*this, s);
   PBMP_HIP(hipStreamSynchronize(s));
+}
+
+void Tree::build_transposed(int N, const int *owner, Dbuf<char> &tmp) {
+  hipStream_t s = stream_;
+  auto view = [&]() {
+    return Boxes{d_start.p, d_end.p, d_level.p, d_parent.p, d_first.p, d_nchild.p};
+  };
+  auto one = [&](const Dbuf<int> &ptr, const Dbuf<int> &box, int n, int chunk, Dbuf<int> &tsub,
+                 Dbuf<int> &ttask, Dbuf<int> &cnt_out, Dbuf<int> &off_task, int &ntasks) {
+    Dbuf<int> key, val, skey, sval, first, last, col, off_sub;
+    const int m = std::max(1, n);
+    key.alloc(m);
+    val.alloc(m);
+    skey.alloc(m);
+    sval.alloc(m);
+    first.alloc(nbox);
+    last.alloc(nbox);
+    hipLaunchKernelGGL(k_fill_int, grid_for(nbox), dim3(256), 0, s, nbox, 0, first.p);
+    hipLaunchKernelGGL(k_fill_int, grid_for(nbox), dim3(256), 0, s, nbox, 0, last.p);
+    if (n > 0) {
+      hipLaunchKernelGGL(k_expand_pairs, grid_for(nleaf), dim3(256), 0, s, nleaf, ptr.p, box.p,
+                         key.p, val.p);
+      size_t bytes = 0;
+      unsigned bits = 1;
+      while ((1u << bits) < (unsigned)nbox) ++bits;
+      PBMP_HIP(rocprim::radix_sort_pairs(nullptr, bytes, key.p, skey.p, val.p, sval.p,
+                                         (size_t)n, 0, bits, s));
+      tmp.reserve(std::max<size_t>(bytes, 1));
+      PBMP_HIP(rocprim::radix_sort_pairs(tmp.p, bytes, key.p, skey.p, val.p, sval.p,
+                                         (size_t)n, 0, bits, s));
+      hipLaunchKernelGGL(k_runs, grid_for(n), dim3(256), 0, s, n, skey.p, first.p, last.p);
+    }
+    cnt_out.alloc(2 * (size_t)nbox);
+    hipLaunchKernelGGL(k_tasks_T<false>, grid_for(nbox, 64), dim3(64), 0, s, nbox, first.p,
+                       last.p, sval.p, d_leaves.p, view(), chunk, cnt_out.p, nullptr, nullptr,
+                       nullptr, nullptr);
+    col.alloc(nbox);
+    off_sub.alloc(nbox);
+    off_task.alloc(nbox);
+    hipLaunchKernelGGL(k_column2, grid_for(nbox), dim3(256), 0, s, nbox, cnt_out.p, 0, col.p);
+    const int nsub = exclusive_scan_total(s, col.p, off_sub.p, nbox, tmp);
+    hipLaunchKernelGGL(k_column2, grid_for(nbox), dim3(256), 0, s, nbox, cnt_out.p, 1, col.p);
+    ntasks = exclusive_scan_total(s, col.p, off_task.p, nbox, tmp);
+    tsub.alloc(2 * (size_t)std::max(1, nsub));
+    ttask.alloc(4 * (size_t)std::max(1, ntasks));
+    hipLaunchKernelGGL(k_tasks_T<true>, grid_for(nbox, 64), dim3(64), 0, s, nbox, first.p,
+                       last.p, sval.p, d_leaves.p, view(), chunk, nullptr, off_sub.p,
+                       off_task.p, tsub.p, ttask.p);
+    PBMP_HIP(hipGetLastError());
+    PBMP_HIP(hipStreamSynchronize(s));
+  };
+  Dbuf<int> p2pT_off;
+  one(d_p2p_ptr, d_p2p_box, n_p2p_entries, kP2PChunkPanels, d_p2pT_sub, d_p2pT_task,
+      d_p2pT_count, p2pT_off, n_p2pT_tasks);
+  one(d_m2p_ptr, d_m2p_box, n_m2p_entries, kM2PTChunkTargets, d_m2pT_sub, d_m2pT_task,
+      d_m2pT_count, d_m2pT_off, n_m2pT_tasks);
+  d_tslotsT.alloc(N);
+  hipLaunchKernelGGL(k_source_slots, grid_for(N), dim3(256), 0, s, N, owner, d_p2pT_count.p,
+                     d_tslotsT.p);
+  PBMP_HIP(hipGetLastError());
+  // largest slot count of a source panel
+  std::vector<int> h(2 * (size_t)nbox);
+  d_p2pT_count.download(h.data(), h.size(), s);
+  PBMP_HIP(hipStreamSynchronize(s));
+  max_slots_T = 1;
+  for (int b = 0; b < nbox; ++b) max_slots_T = std::max(max_slots_T, h[2 * b + 1] + 1);
 }
 
 }  // namespace pbmp

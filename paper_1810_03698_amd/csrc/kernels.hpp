@@ -141,6 +141,13 @@ void tree_apply(Tree &t, hipStream_t s, bool fp64, int nf, int N,
                 const float *tgt32, double kappa, double *part, KernelClock &clk,
                 bool floor_r2);
 // finish with a per-target number of partial slots
+// A^T z with the treecode (transposed P2P, M2P^T + L2L + L2P, transposed
+// near/self correction)
+void tree_apply_transpose(Tree &t, hipStream_t s, bool fp64, int nf, int N, const double *geo,
+                          const double *src64, const float *src32, const float *tgt32,
+                          const double *z, double kappa, double *part, const int *trow,
+                          const int *tcol, const int *tent, const double *val, double eps_ratio,
+                          double *y);
 void launch_finish_slots(hipStream_t s, int N, const int *tslots,
                          const double *part, const int *rowptr, const int *col,
                          const double *val, const double *x, double eps_ratio,

@@ -5,6 +5,7 @@
 #include "runtime.hpp"
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -360,6 +361,15 @@ void Runtime::build_near_lists() {
   diag_.alloc(2 * (size_t)N);
   launch_near_values(s_, fp64(), N, nrow_.p, ncol_.p, verts_.p, tri_.p, geo_.p,
                      src64_.p, src32_.p, tgt32_.p, ru_, o.kappa, nval_.p, diag_.p);
+  if (!fp64()) {
+    // corrections against the FP64 far field, for the FP64 residual
+    // products of the refinement in GMRES
+    nval64_.alloc(4 * col.size());
+    launch_near_values(s_, true, N, nrow_.p, ncol_.p, verts_.p, tri_.p, geo_.p, src64_.p,
+                       src32_.p, tgt32_.p, ru_, o.kappa, nval64_.p, diag_.p);
+  } else {
+    nval64_.release();
+  }
   // transposed structure: for column j, the entry ids e with col[e] == j
   std::vector<int> trow(N + 1, 0), tent(col.size()), tcol(col.size());
   for (int c : col) trow[c + 1]++;
@@ -386,7 +396,7 @@ void Runtime::alloc_work() {
   const int bx = (N + 256 * tpt - 1) / (256 * tpt);
   p2p_chunks_ = std::max(1, std::min((2048 + bx - 1) / bx, (N + 127) / 128));
   int slots = p2p_chunks_;
-  if (tree_active_) slots = std::max(slots, tree_->max_slots);
+  if (tree_active_) slots = std::max({slots, tree_->max_slots, tree_->max_slots_T});
   part_.alloc((size_t)slots * 4 * N);
   V_.alloc((size_t)(m + 1) * n);
   w_.alloc(n);
@@ -479,16 +489,21 @@ void Runtime::set_sites(int64_t m, const double *xyz, const double *q,
   solved_ = false;
 }
 
-void Runtime::build_site_lists() {
-  const int N = N_, M = M_;
+// panels j with |p_l - c_j| < eta sqrt(A_j) for the points p (AoS) as CSR
+// (row [M+1], col sorted per row; col holds at least one entry)
+void Runtime::point_lists(const std::vector<double> &pts, int M, std::vector<int> &row,
+                          std::vector<int> &col) const {
+  const int N = N_;
   const double *g = h_geo_.data();
   double rmax = 0.0;
   for (int j = 0; j < N; ++j) rmax = std::max(rmax, o.near_eta * std::sqrt(g[6 * N + j]));
   Grid grid;
   grid.build(h_geo_, N, std::max(rmax, 1e-9));
-  std::vector<int> row(M + 1, 0), col, tmp;
+  row.assign(M + 1, 0);
+  col.clear();
+  std::vector<int> tmp;
   for (int l = 0; l < M; ++l) {
-    const double x = h_sxyz_[3 * l], y = h_sxyz_[3 * l + 1], z = h_sxyz_[3 * l + 2];
+    const double x = pts[3 * l], y = pts[3 * l + 1], z = pts[3 * l + 2];
     tmp.clear();
     grid.visit(x, y, z, [&](int j) {
       const double dx = x - g[j], dy = y - g[N + j], dz = z - g[2 * N + j];
@@ -499,6 +514,12 @@ void Runtime::build_site_lists() {
     col.insert(col.end(), tmp.begin(), tmp.end());
     row[l + 1] = (int)col.size();
   }
+}
+
+void Runtime::build_site_lists() {
+  const int N = N_, M = M_;
+  std::vector<int> row, col;
+  point_lists(h_sxyz_, M, row, col);
   // per panel: the sites for which it is near (transposed lists)
   std::vector<int> trow(N + 1, 0), tcol(std::max<size_t>(1, col.size()), 0);
   for (int l = 0; l < M; ++l)
@@ -516,22 +537,28 @@ void Runtime::build_site_lists() {
 }
 
 // -------------------------------------------------------------- operator
-void Runtime::apply(const double *x, double *y) {
+void Runtime::apply(const double *x, double *y, bool f64) {
   const int N = N_;
+  const bool use64 = f64 || fp64();
+  const double *val = (use64 && !fp64()) ? nval64_.p : nval_.p;
+  // refinement products are FP64 by request: kept out of the kernel timers
+  const bool timed = clock.on;
+  if (f64 && !fp64()) clock.on = false;
   launch_pack_strengths(s_, N, ru_.nf, geo_.p, x, src64_.p, src32_.p);
   if (use_tree()) {
-    tree_apply(*tree_, s_, fp64(), ru_.nf, N, geo_.p, src64_.p, src32_.p,
+    tree_apply(*tree_, s_, use64, ru_.nf, N, geo_.p, src64_.p, src32_.p,
                tgt32_.p, o.kappa, part_.p, clock, floor_r2_);
     launch_finish_slots(s_, N, tree_->d_tslots.p, part_.p, nrow_.p, ncol_.p,
-                        nval_.p, x, o.eps_in / o.eps_out, y);
+                        val, x, o.eps_in / o.eps_out, y);
   } else {
     hipEvent_t e0 = clock.on ? clock.begin(s_) : nullptr;
-    launch_p2p_direct(s_, fp64(), ru_.nf, N, N, src64_.p, src32_.p, geo_.p,
+    launch_p2p_direct(s_, use64, ru_.nf, N, N, src64_.p, src32_.p, geo_.p,
                       tgt32_.p, o.kappa, p2p_chunks_, part_.p, floor_r2_);
     if (clock.on) clock.end(s_, e0, KernelClock::P2P, (double)N * N * ru_.nf);
-    launch_finish(s_, N, p2p_chunks_, part_.p, nrow_.p, ncol_.p, nval_.p, x,
+    launch_finish(s_, N, p2p_chunks_, part_.p, nrow_.p, ncol_.p, val, x,
                   o.eps_in / o.eps_out, y);
   }
+  clock.on = timed;
   ++matvecs_;
 }
 
@@ -542,10 +569,16 @@ void Runtime::apply(const double *x, double *y) {
 int Runtime::gmres(const double *b, double *x, bool transpose, int *iters) {
   const int N = N_, n = 2 * N, m = o.gmres_restart;
   const size_t ld = n;
-  auto op = [&](const double *in, double *out) {
-    if (transpose) apply_transpose(in, out);
-    else apply(in, out);
+  auto op = [&](const double *in, double *out, bool f64) {
+    if (transpose) apply_transpose(in, out, f64);
+    else apply(in, out, f64);
   };
+  // Mixed precision: restart residuals come from the FP32-far-field product
+  // while they keep falling; once a cycle stalls (the residual floor of that
+  // product), they are recomputed with the FP64 product, which turns the
+  // restarts into iterative refinement with FP64 residuals.
+  bool refine = false;
+  double prev = 0.0;
   auto dot_host = [&](const double *a, const double *bb) {
     launch_mdot(s_, n, 1, a, ld, bb, partial_.p, hbuf_.p);
     double h;
@@ -563,10 +596,17 @@ int Runtime::gmres(const double *b, double *x, bool transpose, int *iters) {
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hh(3 * (m + 2)), y(m);
   int it = 0;
   while (true) {
-    op(x, ax_.p);
+    op(x, ax_.p, refine);
     launch_xmy(s_, n, b, ax_.p, w_.p);
-    const double beta = std::sqrt(dot_host(w_.p, w_.p));
+    double beta = std::sqrt(dot_host(w_.p, w_.p));
+    if (!refine && !fp64() && it > 0 && beta / bnorm > 0.5 * prev && beta / bnorm > o.gmres_tol) {
+      refine = true;
+      op(x, ax_.p, true);
+      launch_xmy(s_, n, b, ax_.p, w_.p);
+      beta = std::sqrt(dot_host(w_.p, w_.p));
+    }
     last_relres_ = beta / bnorm;
+    prev = last_relres_;
     if (last_relres_ <= o.gmres_tol) return 0;
     if (it >= o.gmres_maxit) return PBMP_WGMRES;
     launch_scale(s_, n, 1.0 / beta, w_.p, V_.p);
@@ -579,7 +619,7 @@ int Runtime::gmres(const double *b, double *x, bool transpose, int *iters) {
         precond_T(vk, z_.p);
       else
         launch_precond(s_, N, diag_.p, o.eps_in / o.eps_out, vk, z_.p);
-      op(z_.p, w_.p);
+      op(z_.p, w_.p, false);
       // CGS2
       launch_mdot(s_, n, k + 1, V_.p, ld, w_.p, partial_.p, hbuf_.p);
       launch_gemv_sub(s_, n, k + 1, V_.p, ld, hbuf_.p, w_.p);
@@ -637,6 +677,108 @@ int Runtime::gmres(const double *b, double *x, bool transpose, int *iters) {
   }
 }
 
+// GMRES for a general operator of size n (right preconditioning, CGS2,
+// Givens on the host, FP64 refinement as in gmres).  x holds the initial
+// guess.
+int Runtime::gmres_generic(int n, const std::function<void(const double *, double *, bool)> &op,
+                           const std::function<void(const double *, double *)> &prec,
+                           const double *b, double *x, int *iters) {
+  const int m = o.gmres_restart;
+  const size_t ld = n;
+  gV_.reserve((size_t)(m + 1) * n);
+  gw_.reserve(n);
+  gz_.reserve(n);
+  gax_.reserve(n);
+  auto dot_host = [&](const double *a, const double *bb) {
+    launch_mdot(s_, n, 1, a, ld, bb, partial_.p, hbuf_.p);
+    double h;
+    PBMP_HIP(hipMemcpyAsync(&h, hbuf_.p, sizeof(double), hipMemcpyDeviceToHost, s_));
+    sync();
+    return h;
+  };
+  const double bnorm = std::sqrt(dot_host(b, b));
+  *iters = 0;
+  if (bnorm == 0.0) {
+    PBMP_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s_));
+    last_relres_ = 0.0;
+    return 0;
+  }
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hh(3 * (m + 2)), y(m);
+  bool refine = false;
+  double prev = 0.0;
+  int it = 0;
+  while (true) {
+    op(x, gax_.p, refine);
+    launch_xmy(s_, n, b, gax_.p, gw_.p);
+    double beta = std::sqrt(dot_host(gw_.p, gw_.p));
+    if (!refine && !fp64() && it > 0 && beta / bnorm > 0.5 * prev && beta / bnorm > o.gmres_tol) {
+      refine = true;
+      op(x, gax_.p, true);
+      launch_xmy(s_, n, b, gax_.p, gw_.p);
+      beta = std::sqrt(dot_host(gw_.p, gw_.p));
+    }
+    last_relres_ = beta / bnorm;
+    prev = last_relres_;
+    if (last_relres_ <= o.gmres_tol) return 0;
+    if (it >= o.gmres_maxit) return PBMP_WGMRES;
+    launch_scale(s_, n, 1.0 / beta, gw_.p, gV_.p);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k_done = 0;
+    for (int k = 0; k < m; ++k) {
+      double *vk = gV_.p + (size_t)k * ld;
+      prec(vk, gz_.p);
+      op(gz_.p, gw_.p, false);
+      launch_mdot(s_, n, k + 1, gV_.p, ld, gw_.p, partial_.p, hbuf_.p);
+      launch_gemv_sub(s_, n, k + 1, gV_.p, ld, hbuf_.p, gw_.p);
+      launch_mdot(s_, n, k + 1, gV_.p, ld, gw_.p, partial_.p, hbuf_.p + (m + 2));
+      launch_gemv_sub(s_, n, k + 1, gV_.p, ld, hbuf_.p + (m + 2), gw_.p);
+      launch_mdot(s_, n, 1, gw_.p, ld, gw_.p, partial_.p, hbuf_.p + 2 * (m + 2));
+      PBMP_HIP(hipMemcpyAsync(hh.data(), hbuf_.p, sizeof(double) * 3 * (m + 2),
+                              hipMemcpyDeviceToHost, s_));
+      sync();
+      for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = hh[i] + hh[m + 2 + i];
+      const double hn = std::sqrt(hh[2 * (m + 2)]);
+      H[(size_t)(k + 1) * m + k] = hn;
+      if (hn > 0)
+        launch_scale_inv_sqrt(s_, n, gw_.p, hbuf_.p + 2 * (m + 2), gV_.p + (size_t)(k + 1) * ld);
+      for (int i = 0; i < k; ++i) {
+        const double a = H[(size_t)i * m + k], bb = H[(size_t)(i + 1) * m + k];
+        H[(size_t)i * m + k] = cs[i] * a + sn[i] * bb;
+        H[(size_t)(i + 1) * m + k] = -sn[i] * a + cs[i] * bb;
+      }
+      const double a = H[(size_t)k * m + k], bb = H[(size_t)(k + 1) * m + k];
+      const double den = std::hypot(a, bb);
+      cs[k] = den > 0 ? a / den : 1.0;
+      sn[k] = den > 0 ? bb / den : 0.0;
+      H[(size_t)k * m + k] = den;
+      H[(size_t)(k + 1) * m + k] = 0.0;
+      g[k + 1] = -sn[k] * g[k];
+      g[k] = cs[k] * g[k];
+      ++it;
+      ++gmres_iters_;
+      k_done = k + 1;
+      if (std::fabs(g[k + 1]) <= 0.5 * o.gmres_tol * bnorm || it >= o.gmres_maxit || hn == 0.0)
+        break;
+    }
+    for (int i = k_done - 1; i >= 0; --i) {
+      double sacc = g[i];
+      for (int j = i + 1; j < k_done; ++j) sacc -= H[(size_t)i * m + j] * y[j];
+      y[i] = sacc / H[(size_t)i * m + i];
+    }
+    // x += M^{-1} (V y)
+    for (int i = 0; i < k_done; ++i) y[i] = -y[i];
+    PBMP_HIP(hipMemcpyAsync(ybuf_.p, y.data(), sizeof(double) * k_done, hipMemcpyHostToDevice,
+                            s_));
+    PBMP_HIP(hipMemsetAsync(gax_.p, 0, sizeof(double) * n, s_));
+    launch_gemv_sub(s_, n, k_done, gV_.p, ld, ybuf_.p, gax_.p);
+    prec(gax_.p, gz_.p);
+    launch_axpy(s_, n, 1.0, gz_.p, x);
+    sync();
+    *iters = it;
+  }
+}
+
 // ------------------------------------------------------------- readout
 void Runtime::readout(const double *x, bool full, double *out) {
   launch_pack_strengths(s_, N_, ru_.nf, geo_.p, x, src64_.p, src32_.p);
@@ -654,6 +796,7 @@ int Runtime::scf(bool solvent, double *mu, int *gm_warn) {
   if (solvent) {
     PBMP_HIP(hipMemsetAsync(x_.p, 0, sizeof(double) * 2 * N, s_));
     PBMP_HIP(hipMemsetAsync(b_.p, 0, sizeof(double) * 2 * N, s_));
+    if (outer_) PBMP_HIP(hipMemsetAsync(sX_.p, 0, sizeof(double) * sX_.n, s_));
   }
   for (int it = 1; it <= o.scf_maxit; ++it) {
     if (solvent) {
@@ -662,7 +805,7 @@ int Runtime::scf(bool solvent, double *mu, int *gm_warn) {
       launch_rhs(s_, fp64(), N, M, geo_.p, sxyz_.p, sq_.p, p_.p, sQ_.p, o.eps_in, b_.p);
       int gi = 0;
       auto tm = clk::now();
-      const int rc = gmres(b_.p, x_.p, false, &gi);
+      const int rc = outer_ ? gmres_stern(b_.p, x_.p, &gi) : gmres(b_.p, x_.p, false, &gi);
       t_matvec_ms_ += ms_since(tm);
       if (rc > 0) *gm_warn = rc;
       readout(x_.p, false, reac_.p);
@@ -773,6 +916,11 @@ void Runtime::to_user(const double *dev, double *user, int blocks, int where) {
 void Runtime::matvec_user(const double *x, double *y, int transpose, int where) {
   PBMP_REQUIRE(N_ > 0, PBMP_ESTATE, "no mesh");
   PBMP_REQUIRE(where == PBMP_HOST || where == PBMP_DEVICE, PBMP_EARG, "bad where");
+  if (outer_) {
+    PBMP_REQUIRE(!transpose, PBMP_ESTATE, "no transposed product with a Stern layer");
+    stern_matvec_user(x, y, where);
+    return;
+  }
   to_internal(x, io_a_.p, 2, where);
   auto t0 = clk::now();
   if (transpose) apply_transpose(io_a_.p, io_b_.p);

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <chrono>
+#include <functional>
 #include <memory>
 #include <string>
 #include <vector>
@@ -55,6 +56,10 @@ class Runtime {
                    double *box_centre, double *box_radius, int32_t *leaf_box,
                    int32_t *m2p_ptr, int32_t *m2p_box, int32_t *p2p_ptr,
                    int32_t *p2p_box) const;
+  // ion-exclusion layer: outer surface G2 and its permittivity (nt = 0 removes it)
+  void set_stern(int64_t nv, const double *verts, int64_t nt, const int32_t *tris,
+                 double eps_stern, int where);
+  bool has_stern() const { return (bool)outer_; }
   int backward(double dGbar, double *g_xyz, double *g_q, double *g_d,
                double *g_Q, double *g_verts, int where);
 
@@ -83,7 +88,7 @@ class Runtime {
   std::vector<int> h_tri_;  // internal order
   Dbuf<int> nrow_, ncol_;
   int nnz_ = 0;
-  Dbuf<double> nval_, diag_;
+  Dbuf<double> nval_, nval64_, diag_;  // nval64_: FP64-far-field corrections (mixed mode)
   Dbuf<int> trow_, tcol_;  // transposed near structure (entry ids)
   Dbuf<int> tent_;
   bool tree_active_ = false;
@@ -115,8 +120,9 @@ class Runtime {
   void build_site_lists();
   void alloc_work();
   // y = A x (internal order, device)
-  void apply(const double *x, double *y);
-  void apply_transpose(const double *x, double *y);
+  // y = A x (transpose: A^T x); f64 forces the FP64 far field in mixed mode
+  void apply(const double *x, double *y, bool f64 = false);
+  void apply_transpose(const double *x, double *y, bool f64 = false);
   void precond_T(const double *u, double *z);
   // GMRES on A x = b (device, internal order), x holds the initial guess.
   int gmres(const double *b, double *x, bool transpose, int *iters);
@@ -127,6 +133,25 @@ class Runtime {
   int scf(bool solvent, double *mu, int *gm_warn);
   void to_internal(const double *user, double *dev, int blocks, int where);
   void to_user(const double *dev, double *user, int blocks, int where);
+  // ---- Stern layer ----
+  std::unique_ptr<Runtime> outer_;  // G2 with eps_in = eps_stern, its own kappa
+  double kappa_ext_ = 0.0, eps_out_ext_ = 0.0, eps_stern_ = 0.0;
+  int Mp_ = 0, p_chunks_ = 1;  // probe points: layer potentials of this surface there
+  Dbuf<double> pxyz_, ppart_, pout_;
+  Dbuf<int> prow_, pcol_;
+  Dbuf<double> sX_, sB_, sY_, sT_;       // [phi1, q1, phi2, q2] work
+  Dbuf<double> gV_, gw_, gz_, gax_;      // general GMRES work
+  void point_lists(const std::vector<double> &pts, int M, std::vector<int> &row,
+                   std::vector<int> &col) const;
+  void set_probe(int M, const std::vector<double> &pts);
+  void probe(const double *x, bool f64, double *out4);
+  void apply_stern(const double *X, double *Y, bool f64);
+  void precond_stern(const double *v, double *z);
+  int gmres_stern(const double *b, double *x, int *iters);
+  void stern_matvec_user(const double *x, double *y, int where);
+  int gmres_generic(int n, const std::function<void(const double *, double *, bool)> &op,
+                    const std::function<void(const double *, double *)> &prec,
+                    const double *b, double *x, int *iters);
   friend struct Backward;
 };
 

@@ -9,11 +9,19 @@
 namespace pbmp {
 
 // boxes per M2P task (one task's moments are staged in LDS)
-constexpr int kM2PChunkBoxes = 16;
+#ifndef PBMP_M2P_CHUNK
+#define PBMP_M2P_CHUNK 16
+#endif
+constexpr int kM2PChunkBoxes = PBMP_M2P_CHUNK;
 // source panels per P2P task: a leaf's source list is cut at this size so
 // that no task is much longer than the others (the launch is short enough
 // for the longest task to set its duration)
-constexpr int kP2PChunkPanels = 256;
+#ifndef PBMP_P2P_CHUNK
+#define PBMP_P2P_CHUNK 256
+#endif
+constexpr int kP2PChunkPanels = PBMP_P2P_CHUNK;
+// target panels per M2P^T task (adjoint product)
+constexpr int kM2PTChunkTargets = 512;
 
 struct TreeParams {
   double theta = 0.5;
@@ -48,6 +56,14 @@ class Tree {
   Dbuf<int> d_m2p_task;   // [4*n] t0, t1, list begin, end
   Dbuf<int> d_m2p_slot;
   Dbuf<int> d_tslots;     // [N] number of slots of the target's leaf
+  // transposed (adjoint) product: P2P^T tasks per source leaf and M2P^T
+  // tasks per accepted box, each over target sub-ranges;
+  // task = (box, sub begin, sub end, slot)
+  Dbuf<int> d_p2pT_sub, d_p2pT_task, d_p2pT_count;  // count[2*box] = (subs, tasks)
+  Dbuf<int> d_m2pT_sub, d_m2pT_task, d_m2pT_count, d_m2pT_off;  // off: first task of a box
+  Dbuf<int> d_tslotsT;    // [N] transposed slots of the panel's leaf (tasks + 1)
+  int n_p2pT_tasks = 0, n_m2pT_tasks = 0, max_slots_T = 1;
+  Dbuf<double> d_Lpart, d_L;  // local coefficients: per M2P^T task, per box [2][ncoef]
   Dbuf<double> d_mom64;   // [nbox][2][ncoef]
   Dbuf<float> d_mom32;    // [nbox][2][ncoef]
   Dbuf<int> d_monos;      // [3*ncoef] exponents
@@ -56,6 +72,10 @@ class Tree {
   // the centroids (geo SoA) and far nodes (src64 records), all on device.
   void build_device(int N, int nf, const uint64_t *key, const double *geo,
                     const double *src64, hipStream_t s);
+
+ private:
+  hipStream_t stream_ = nullptr;
+  void build_transposed(int N, const int *owner, Dbuf<char> &tmp);
 };
 
 // Morton order of the panels on the device: perm[i] = caller's index of the

@@ -61,7 +61,7 @@ _lib = None
 SYMBOLS = ["pbmp_default_options", "pbmp_create", "pbmp_set_mesh",
            "pbmp_set_sites", "pbmp_solve", "pbmp_matvec", "pbmp_rhs",
            "pbmp_site_fields", "pbmp_backward", "pbmp_last_error",
-           "pbmp_destroy", "pbmp_kernel_stats", "pbmp_tree_export"]
+           "pbmp_destroy", "pbmp_kernel_stats", "pbmp_tree_export", "pbmp_set_stern"]
 
 
 def _torch_runtime_first():
@@ -103,9 +103,10 @@ def load():
     lib.pbmp_destroy.restype = None
     lib.pbmp_kernel_stats.argtypes = [P, I, ctypes.POINTER(KernelStats)]
     lib.pbmp_tree_export.argtypes = [P] * 12
+    lib.pbmp_set_stern.argtypes = [P, L, P, L, P, D, I]
     for name in ("pbmp_create", "pbmp_set_mesh", "pbmp_set_sites", "pbmp_solve",
                  "pbmp_matvec", "pbmp_rhs", "pbmp_site_fields", "pbmp_backward",
-                 "pbmp_kernel_stats", "pbmp_tree_export"):
+                 "pbmp_kernel_stats", "pbmp_tree_export", "pbmp_set_stern"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -207,7 +208,20 @@ class Solver:
         v, t = _Arg(verts, np.float64, 3 * nv), _Arg(tris, np.int32, 3 * nt)
         self._check(self.lib.pbmp_set_mesh(self.ctx, nv, v.ptr, nt, t.ptr,
                                            _common_where([v, t])))
-        self.nt, self.nv = nt, nv
+        self.nt, self.nv, self.nt2 = nt, nv, 0
+
+    def set_stern(self, verts, tris, eps_stern):
+        """Enclosing ion-exclusion surface (see pbmp_set_stern); tris=None
+        removes it."""
+        if tris is None:
+            self._check(self.lib.pbmp_set_stern(self.ctx, 0, None, 0, None, float(eps_stern), HOST))
+            self.nt2 = 0
+            return
+        nv, nt = len(verts), len(tris)
+        v, t = _Arg(verts, np.float64, 3 * nv), _Arg(tris, np.int32, 3 * nt)
+        self._check(self.lib.pbmp_set_stern(self.ctx, nv, v.ptr, nt, t.ptr, float(eps_stern),
+                                            _common_where([v, t])))
+        self.nt2 = nt
 
     def set_sites(self, xyz, q, d, Q9, alpha, group=None):
         m = len(q)
@@ -241,10 +255,11 @@ class Solver:
         return out
 
     def matvec(self, x, transpose=False, out=None):
-        a = _Arg(x, np.float64, 2 * self.nt)
+        n = 2 * self.nt + 2 * getattr(self, "nt2", 0)
+        a = _Arg(x, np.float64, n)
         if out is None:
-            out = np.empty(2 * self.nt) if a.where == HOST else _empty_like_torch(x)
-        o = _Arg(out, np.float64, 2 * self.nt)
+            out = np.empty(n) if a.where == HOST else _empty_like_torch(x)
+        o = _Arg(out, np.float64, n)
         self._check(self.lib.pbmp_matvec(self.ctx, a.ptr, o.ptr, int(transpose),
                                          _common_where([a, o])))
         return out

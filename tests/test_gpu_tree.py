@@ -166,3 +166,70 @@ def test_tree_lists_match_oracle(name, leaf, theta, sph5120):
             ties += 1
     assert ties <= 2
     print(name, "boxes", len(boxes), "leaves", len(lists), "ties", ties)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 2e-5)])
+def test_tree_transpose_is_exact_adjoint(precision, tol, sph5120):
+    """The treecode's transposed product (P2P^T, M2P^T, L2L, L2P, transposed
+    corrections) is the exact transpose of its forward product:
+    <z, A x> = <A^T z, x> up to rounding."""
+    s = _solver(sph5120, precision=precision)
+    rng = np.random.default_rng(31)
+    N = len(sph5120["tris"])
+    for _ in range(2):
+        x, z = rng.normal(size=2 * N), rng.normal(size=2 * N)
+        lhs = z @ s.matvec(x)
+        rhs = s.matvec(z, transpose=True) @ x
+        scale = np.linalg.norm(z) * np.linalg.norm(x)
+        print(precision, lhs, rhs, abs(lhs - rhs) / scale)
+        assert abs(lhs - rhs) < tol * scale
+
+
+def test_tree_transpose_vs_oracle(sph5120):
+    """A^T z against the oracle's dense transpose, at the treecode's accuracy."""
+    m = bie.Mesh(sph5120["verts"], sph5120["tris"], 0.125)
+    A = bie.dense_system(m, 1.0, 80.0)
+    z = np.random.default_rng(33).normal(size=2 * m.N)
+    ref = A.T @ z
+    del A
+    for precision in ("fp64", "mixed"):
+        s = _solver(sph5120, precision=precision)
+        y = s.matvec(z, transpose=True)
+        err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+        print(precision, "transpose error", err)
+        assert err < 5e-4
+
+
+def test_tree_backward_matches_fd():
+    """Site-position and multipole gradients in treecode mode against
+    central differences of the treecode solve itself (the adjoint solve
+    uses the exact transposed treecode product)."""
+    from tests.test_gpu_direct import _ragged
+    w = _ragged()
+    kw = dict(precision="fp64", gmres_tol=1e-13, scf_tol_debye=1e-11, scf_maxit=500,
+              leaf_panels=50)
+    s = _solver(w, **kw)
+    s.solve(outputs=False)
+    g = s.backward(1.0)
+
+    def energy(xyz=None, q=None):
+        t = _solver(dict(w, xyz=w["xyz"] if xyz is None else xyz,
+                         q=w["q"] if q is None else q), **kw)
+        return t.solve(outputs=False)["dG"]
+
+    rng = np.random.default_rng(5)
+    h = 1e-4
+    for l in rng.choice(len(w["q"]), 3, replace=False):
+        for a in range(3):
+            xp, xm = w["xyz"].copy(), w["xyz"].copy()
+            xp[l, a] += h
+            xm[l, a] -= h
+            fd = (energy(xyz=xp) - energy(xyz=xm)) / (2 * h)
+            print("xyz", l, a, g["xyz"][l, a], fd)
+            assert abs(g["xyz"][l, a] - fd) < 1e-6 * max(1.0, abs(fd))
+        qp, qm = w["q"].copy(), w["q"].copy()
+        qp[l] += 1e-5
+        qm[l] -= 1e-5
+        fd = (energy(q=qp) - energy(q=qm)) / 2e-5
+        print("q", l, g["q"][l], fd)
+        assert abs(g["q"][l] - fd) < 1e-6 * max(1.0, abs(fd))

@@ -498,3 +498,55 @@ def test_vacuum_binding_vanishes_at_separation():
     e = [abs(v - lead / s) for v, s in zip(vals, (10.0, 100.0, 1000.0))]
     assert e[2] < 1e-2 * abs(lead / 1000.0)
     assert 50 < e[1] / e[2] < 200
+
+
+# ------------------------------------------------------------ Stern layer
+def test_stern_coefficients_reduce_and_solve_the_matching():
+    """Kirkwood coefficients with an ion-exclusion shell: a shell of zero
+    thickness gives the sphere's coefficients; a shell of the outer medium
+    without salt changes nothing; and each f_n solves the four matching
+    conditions (phi and eps dphi/dr continuous at a and b) written as a
+    linear system."""
+    from oracle import kirkwood as kw
+    a, b, e1, es, eo, kap = 4.0, 5.0, 4.0, 30.0, 80.0, 0.125
+    f_sph = kw.f_coefficients(25, a, e1, eo, kap)
+    assert np.abs(kw.f_coefficients(25, a, e1, eo, kap, b=a, eps_stern=es) - f_sph).max() < 1e-13
+    assert np.abs(kw.f_coefficients(25, a, e1, eo, 0.0, b=b, eps_stern=eo)
+                  - kw.f_coefficients(25, a, e1, eo, 0.0)).max() < 1e-13
+    f = kw.f_coefficients(25, a, e1, eo, kap, b=b, eps_stern=es)
+    g = kw.g_coefficients(25, kap * b)
+    for n in range(0, 26, 5):
+        # unknowns A, B, C, D (interior r^n, shell r^n and r^-(n+1), exterior
+        # value at b); source s r^-(n+1) with s = 1
+        M = np.array([
+            [a ** n, -a ** n, -a ** -(n + 1), 0.0],
+            [e1 * n * a ** (n - 1) if n else 0.0, -es * n * a ** (n - 1) if n else 0.0,
+             es * (n + 1) * a ** -(n + 2), 0.0],
+            [0.0, b ** n, b ** -(n + 1), -1.0],
+            [0.0, es * n * b ** (n - 1) if n else 0.0, -es * (n + 1) * b ** -(n + 2),
+             -eo * g[n] / b]])
+        rhs = np.array([-a ** -(n + 1), e1 * (n + 1) * a ** -(n + 2), 0.0, 0.0])
+        A = np.linalg.solve(M, rhs)[0]
+        assert abs(A * a ** (2 * n + 1) - f[n]) < 1e-10 * max(1.0, abs(f[n]))
+
+
+@pytest.mark.slow
+def test_stern_bem_converges_to_series():
+    """The two-surface system on icospheres (4 A and 5 A) approaches the
+    Stern-layer series for point charges at O(h^2): error ratio ~4 per
+    subdivision."""
+    from oracle import kirkwood as kw, stern, solver as osolver
+    from synth import icosphere
+    xyz = np.array([[0.0, 0, 0], [2.0, 0, 0], [0, 1.5, 0.5]])
+    q = np.array([1.0, -0.5, 0.3])
+    Z3, Z9, al = np.zeros((3, 3)), np.zeros((3, 9)), np.zeros(3)
+    ref = osolver.solvation(xyz, q, Z3, Z9, al,
+                            kw.SphereSolvent(4.0, 4.0, 80.0, 0.125, b=5.0, eps_stern=80.0),
+                            eps_in=4.0)["dG"]
+    errs = []
+    for lev in (2, 3):
+        v1, t1 = icosphere(lev, 4.0)
+        v2, t2 = icosphere(lev, 5.0)
+        sb = stern.SternBemSolvent(v1, t1, v2, t2, 4.0, 80.0, 80.0, 0.125)
+        errs.append(abs(osolver.solvation(xyz, q, Z3, Z9, al, sb, eps_in=4.0)["dG"] - ref) / abs(ref))
+    assert errs[0] < 0.03 and 3.5 < errs[0] / errs[1] < 4.6
