@@ -23,6 +23,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 COPY_BYTES = 256 << 20
+
+# HBM traffic of the dominant kernel per launch, from two rocprofv3 --pmc
+# passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean over the dispatches
+# of one solve) scaled by what the counters read for a 256 MiB copy
+# (FETCH_SIZE reads 0.5004 of the bytes read, WRITE_SIZE 1.0 of the bytes
+# written).  Keyed by (mode, kernel); valid only while the sources of the
+# kernel hash to the recorded value (otherwise traffic is reported null).
+TRAFFIC = {}
+TRAFFIC_SOURCES = {
+    ("treecode", "p2p"): ["k_tree.hip", "pair.hpp", "tree.hpp", "k_treebuild.hip"],
+    ("direct", "p2p"): ["k_p2p.hip", "pair.hpp"],
+}
+
+
+def _sources_hash(files):
+    import hashlib
+    h = hashlib.sha256()
+    root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1810_03698_amd", "csrc")
+    for f in files:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_bytes(mode, kernel):
+    rec = TRAFFIC.get((mode, kernel))
+    if rec is None or rec["sha"] != _sources_hash(TRAFFIC_SOURCES[(mode, kernel)]):
+        return None
+    return rec["fetch_kib"] * 1024 / rec["fetch_scale"] + rec["write_kib"] * 1024 / rec["write_scale"]
 ALG_FLOP_PER_PAIR = 33  # four kernels per (target, far-field node) pair
 PEAK_FP32_VECTOR = 157.3  # TFLOP/s, MI355X published (packed FP32)
 PEAK_FP32_NONPACKED = 78.6  # 256 CU x 64 lanes x 2 FLOP x 2.4 GHz
@@ -196,7 +225,8 @@ def main():
     achieved = per_launch / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
-                "traffic": None, "kernel": name, "avg_launch_ms": avg_ms,
+                "traffic": traffic_bytes(mode, name), "traffic_unit": "bytes per launch",
+                "kernel": name, "avg_launch_ms": avg_ms,
                 "frac_of_nonpacked_fp32": achieved / PEAK_FP32_NONPACKED,
                 "p2p_ms_total": st["p2p_ms"], "m2p_ms_total": st["m2p_ms"],
                 "p2m_ms_total": st["p2m_ms"],

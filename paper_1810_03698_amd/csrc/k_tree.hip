@@ -13,8 +13,9 @@
 //   single layer  m_k  = sum_nodes s_V h^k,
 //   double layer  mK_k = sum_nodes s_K sum_i k_i n_i h^{k-e_i}
 // (the double-layer kernel is n.grad_y G) give V = sum a_k m_k and
-// K = sum a_k mK_k.  Moments are formed at the leaves (P2M) and shifted up
-// the tree (M2M, binomial expansion of (h + t)^k), in FP64.
+// K = sum a_k mK_k.  Moments are formed in FP64 for every box that some
+// target leaf accepts, directly from the box's nodes (P2M per box, one
+// launch; no upward shifts).
 #include <cmath>
 
 #include "kernels.hpp"
@@ -80,21 +81,26 @@ __device__ inline int xcd_task(int ntasks) {
 }
 
 // ---------------------------------------------------------------- P2M
-// One 256-lane block per leaf; every lane takes nodes of the leaf, builds
-// all monomials h^k incrementally (each from its parent multi-index) and
-// accumulates both moment sets in registers; then a wave reduction
-// (shuffles) and an LDS reduction across the four waves.
+// Moments of every box that some target leaf accepts, straight from its
+// nodes (every box is a contiguous panel range): one 256-lane block per
+// task, a task being a box's panels [s0, s1) or a slice of at most
+// kMomChunkPanels of them.  Every lane takes nodes, builds all monomials h^k
+// incrementally (each from its parent multi-index) and accumulates both
+// moment sets in registers; a wave reduction (shuffles) and an LDS reduction
+// across the four waves give the task's partial moments, and k_mom_reduce
+// adds a box's slices in a fixed order.  Computing every level from the
+// nodes replaces the upward shifts (M2M) with one launch and no
+// accumulated shift rounding.
 template <int P>
-__global__ __launch_bounds__(256) void k_p2m(int nf, const int *__restrict__ leaves,
-                                             const int *__restrict__ range,
-                                             const double *__restrict__ center,
-                                             const double *__restrict__ src,
-                                             double *__restrict__ mom) {
+__global__ __launch_bounds__(256) void k_p2m_tasks(int nf, const int *__restrict__ tasks,
+                                                   const double *__restrict__ center,
+                                                   const double *__restrict__ src,
+                                                   double *__restrict__ part) {
   constexpr Multi<P> mi{};
   constexpr int NC = Multi<P>::n;
   __shared__ double red[4][2 * NC];
-  const int B = leaves[blockIdx.x];
-  const int s0 = range[2 * B], s1 = range[2 * B + 1];
+  const int B = tasks[3 * blockIdx.x];
+  const int s0 = tasks[3 * blockIdx.x + 1], s1 = tasks[3 * blockIdx.x + 2];
   const double c[3] = {center[3 * B], center[3 * B + 1], center[3 * B + 2]};
   double m[NC], mk[NC];
 #pragma unroll
@@ -138,64 +144,21 @@ __global__ __launch_bounds__(256) void k_p2m(int nf, const int *__restrict__ lea
   }
   __syncthreads();
   for (int k = threadIdx.x; k < 2 * NC; k += 256)
-    mom[(size_t)B * 2 * NC + k] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+    part[(size_t)blockIdx.x * 2 * NC + k] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
 }
 
-// ---------------------------------------------------------------- M2M
-// (h + t)^k = sum_{j <= k} C(k, j) t^{k-j} h^j, t = child centre - parent
-// centre; one block per box of a level (leaves return at once), one lane
-// per coefficient.  The
-// children's moments are staged in LDS first (one coalesced read), so the
-// shift itself runs at LDS latency.
-template <int P>
-__global__ __launch_bounds__(64) void k_m2m(int base, const int *__restrict__ child,
-                                            const double *__restrict__ center,
-                                            double *__restrict__ mom) {
-  constexpr Multi<P> mi{};
-  constexpr int NC = Multi<P>::n;
-  __shared__ double tp[8][3][P + 1];
-  __shared__ double cm[8][2 * NC];
-  __shared__ int cid[8];
-  const int B = base + (int)blockIdx.x;
-  if (threadIdx.x < 8) cid[threadIdx.x] = child[8 * B + threadIdx.x];
-  __syncthreads();
-  int nch = 0;
-  for (int cc = 0; cc < 8; ++cc) nch += cid[cc] >= 0;
-  if (nch == 0) return;  // a leaf: its moments come from P2M (uniform per block)
-  if (threadIdx.x < 3 * nch) {
-    const int cc = threadIdx.x / 3, d = threadIdx.x % 3;
-    const double t = center[3 * cid[cc] + d] - center[3 * B + d];
-    double p = 1.0;
-    for (int e = 0; e <= P; ++e) {
-      tp[cc][d][e] = p;
-      p *= t;
-    }
-  }
-  for (int e = threadIdx.x; e < nch * 2 * NC; e += 64) {
-    const int cc = e / (2 * NC), k = e % (2 * NC);
-    cm[cc][k] = mom[(size_t)cid[cc] * 2 * NC + k];
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < NC; k += 64) {
-    const int kx = mi.e[k][0], ky = mi.e[k][1], kz = mi.e[k][2];
-    double m = 0.0, mkk = 0.0;
-    for (int cc = 0; cc < nch; ++cc) {
-      for (int jx = 0; jx <= kx; ++jx) {
-        const double wx = kBinom[kx][jx] * tp[cc][0][kx - jx];
-        for (int jy = 0; jy <= ky; ++jy) {
-          const double wxy = wx * kBinom[ky][jy] * tp[cc][1][ky - jy];
-          for (int jz = 0; jz <= kz; ++jz) {
-            const int jd = Multi<P>::index(jx, jy, jz);
-            const double w = wxy * kBinom[kz][jz] * tp[cc][2][kz - jz];
-            m += w * cm[cc][jd];
-            mkk += w * cm[cc][NC + jd];
-          }
-        }
-      }
-    }
-    mom[(size_t)B * 2 * NC + k] = m;
-    mom[(size_t)B * 2 * NC + NC + k] = mkk;
-  }
+// mom[B] = sum of the partial moments of B's slices, in slice order
+__global__ void k_mom_reduce(int nbox, int ncoef2, const int *__restrict__ first,
+                             const int *__restrict__ count, const double *__restrict__ part,
+                             double *__restrict__ mom) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nbox * ncoef2) return;
+  const int B = e / ncoef2, k = e % ncoef2;
+  const int t0 = first[B], nt = count[B];
+  if (nt == 0) return;  // never accepted: no moments needed
+  double v = 0.0;
+  for (int t = t0; t < t0 + nt; ++t) v += part[(size_t)t * ncoef2 + k];
+  mom[e] = v;
 }
 
 __global__ void k_cast(size_t n, const double *__restrict__ a, float *__restrict__ b) {
@@ -208,10 +171,10 @@ __global__ void k_cast(size_t n, const double *__restrict__ a, float *__restrict
 // task's panel sub-ranges, streamed through LDS.  Leaves are often much
 // smaller than a wave, so the lanes are split into G groups of L = 64 / G:
 // every group holds all targets (TPT per lane) and takes every G-th source
-// panel of a tile; the groups' FP64 sums are added in LDS in a fixed order.
-// G and TPT are chosen per task to use the most lanes.  The LDS tile is
-// small and the groups' sums meet through lane shuffles, so a task holds
-// 2 KB of LDS and many waves fit on a CU.
+// panel of a tile; group 0 adds the other groups' FP64 sums through lane
+// shuffles in a fixed order.  G and TPT are chosen per task to use the most
+// lanes.  Tile, TPT bound and the use of groups are compile-time settings
+// (the defaults were the fastest measured; M2P runs without groups).
 #ifndef PBMP_P2P_TILE
 #define PBMP_P2P_TILE 128
 #endif
@@ -222,7 +185,7 @@ __global__ void k_cast(size_t n, const double *__restrict__ a, float *__restrict
 #define PBMP_P2P_GROUPS 1
 #endif
 #ifndef PBMP_M2P_GROUPS
-#define PBMP_M2P_GROUPS 1
+#define PBMP_M2P_GROUPS 0
 #endif
 constexpr int kTileT = PBMP_P2P_TILE;
 constexpr int kMaxTPT = PBMP_P2P_MAXTPT;
@@ -417,8 +380,9 @@ __global__ __launch_bounds__(64) void k_m2p_tasks(int ntask, const int *__restri
     smom[e] = mom[(size_t)boxes[lb + b] * 2 * NC + c];
   }
   for (int e = threadIdx.x; e < nb * 3; e += 64) scen[e] = (T)center[3 * boxes[lb + e / 3] + e % 3];
-  // lanes in G groups of L = 64 / G: a group takes every G-th box for all
-  // targets; G maximises the useful fraction nt nb / (64 ceil(nt/L) ceil(nb/G))
+  // optionally lanes in G groups of L = 64 / G (PBMP_M2P_GROUPS): a group
+  // takes every G-th box for all targets, G maximising the useful fraction
+  // nt nb / (64 ceil(nt/L) ceil(nb/G)); off by default (measured slower)
   int G = 1;
   {
     float be = 0.0f;
@@ -542,15 +506,13 @@ void launch_m2p(Tree &t, hipStream_t s, const T *mom, const T *tgt, int N, T kap
 }
 
 template <int P> void launch_moments_p(Tree &t, hipStream_t s, int nf, const double *src64) {
-  hipLaunchKernelGGL(k_p2m<P>, dim3(t.nleaf), dim3(256), 0, s, nf, t.d_leaves.p, t.d_range.p,
-                     t.d_center.p, src64, t.d_mom64.p);
-  // levels bottom-up; the deepest level holds leaves only
-  for (int l = t.depth - 1; l >= 0; --l) {
-    const int nb = t.level_start[l + 1] - t.level_start[l];
-    if (nb > 0)
-      hipLaunchKernelGGL(k_m2m<P>, dim3(nb), dim3(64), 0, s, t.level_start[l], t.d_child.p,
-                         t.d_center.p, t.d_mom64.p);
-  }
+  constexpr int NC = Multi<P>::n;
+  if (t.n_mom_tasks == 0) return;
+  hipLaunchKernelGGL(k_p2m_tasks<P>, dim3(t.n_mom_tasks), dim3(256), 0, s, nf, t.d_mom_task.p,
+                     t.d_center.p, src64, t.d_mom_part.p);
+  const int n = t.nbox * 2 * NC;
+  hipLaunchKernelGGL(k_mom_reduce, dim3((n + 255) / 256), dim3(256), 0, s, t.nbox, 2 * NC,
+                     t.d_mom_first.p, t.d_mom_count.p, t.d_mom_part.p, t.d_mom64.p);
 }
 
 void launch_moments(Tree &t, hipStream_t s, int nf, const double *src64) {

@@ -8,7 +8,7 @@
 //     that holds more than `leaf` panels, a child starts wherever the next
 //     three key bits (the octant one level down) change.  A scan of those
 //     flags numbers the children, so box ids run level by level and, within
-//     a level, in key order.
+//     a level, in key order; the target leaves are listed in key order.
 //  3. Box geometry: the expansion centre is the midpoint of the bounding box
 //     of the box's far nodes, R_B the largest node distance from it, R_T the
 //     largest centroid distance.
@@ -17,7 +17,8 @@
 //     a leaf that fails goes to the P2P list; other boxes are opened.  A
 //     counting pass sizes everything, scans give offsets, and a second pass
 //     writes the lists, the P2P tasks (the leaf's source panels cut into
-//     chunks of at most `chunk` panels, as sub-ranges), the M2P tasks and the
+//     chunks, as sub-ranges, sized so that every task carries about the same
+//     number of target-source pairs), the M2P tasks (likewise) and the
 //     partial-sum slot of every task.
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
@@ -161,15 +162,18 @@ __global__ void k_owner(int N, int l, int base, const int *__restrict__ flag,
   if (b.level[B] == l && b.nchild[B] > 0) owner[i] = base + idx[i] + flag[i] - 1;
 }
 
-__global__ void k_leaf_flags(int nbox, Boxes b, int *__restrict__ flag) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < nbox) flag[k] = b.nchild[k] == 0;
+// leaves in key order (the order of their panel ranges): a panel that
+// starts its leaf flags it; the leaf containing panel i is owner[i]
+__global__ void k_leaf_flags(int N, const int *__restrict__ owner, Boxes b,
+                             int *__restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) flag[i] = b.start[owner[i]] == i;
 }
 
-__global__ void k_leaf_list(int nbox, const int *__restrict__ flag, const int *__restrict__ idx,
-                            int *__restrict__ leaves) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < nbox && flag[k]) leaves[idx[k]] = k;
+__global__ void k_leaf_list(int N, const int *__restrict__ flag, const int *__restrict__ idx,
+                            const int *__restrict__ owner, int *__restrict__ leaves) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N && flag[i]) leaves[idx[i]] = owner[i];
 }
 
 // ranges and the 8-wide child table in the layout of the product kernels
@@ -238,6 +242,15 @@ __global__ __launch_bounds__(64) void k_box_geometry(int nbox, int nf, int N, Bo
 }
 
 // ---- interaction lists -------------------------------------------------
+// Sources per task for a leaf of nt targets when every task should carry
+// about `work` target-source pairs: the launches are short, so the longest
+// task sets their duration and tasks of equal work keep every wave busy to
+// the end.
+constexpr int kMinChunk = 32, kMaxChunk = 4096;
+__device__ inline int task_chunk(int work, int nt, int lo, int hi) {
+  return min(hi, max(lo, work / max(1, nt)));
+}
+
 struct ListOut {
   // counting pass: per leaf [8]: n_m2p, n_p2p, n_sub, n_ptask, n_mtask,
   // p2p panels, targets, spare
@@ -258,6 +271,10 @@ __global__ void k_lists(int nleaf, const int *__restrict__ leaves, Boxes b,
   const double cT[3] = {center[3 * T], center[3 * T + 1], center[3 * T + 2]};
   const double RT = radius[2 * T + 1];
   const int t0 = b.start[T], t1 = b.end[T];
+  // equal work per task: chunk and mchunk arrive as target-source pairs per
+  // task and become sources per task for this leaf's size
+  chunk = task_chunk(chunk, t1 - t0, kMinChunk, kMaxChunk);
+  mchunk = task_chunk(mchunk, t1 - t0, 1, kM2PChunkBoxes);
   int nm = 0, np = 0, nsub = 0, ntask = 0, cnt = 0, panels = 0;
   int om = 0, op = 0, os = 0, ot = 0, firstsub = 0;
   if (FILL) {
@@ -402,11 +419,14 @@ __global__ void k_fill_int(int n, int v, int *__restrict__ a) {
 template <bool FILL>
 __global__ void k_tasks_T(int nbox, const int *__restrict__ first, const int *__restrict__ last,
                           const int *__restrict__ val, const int *__restrict__ leaves, Boxes b,
-                          int chunk, int *__restrict__ count, const int *__restrict__ off_sub,
+                          int chunk, bool per_source, int *__restrict__ count,
+                          const int *__restrict__ off_sub,
                           const int *__restrict__ off_task, int *__restrict__ sub,
                           int *__restrict__ task) {
   const int B = blockIdx.x * blockDim.x + threadIdx.x;
   if (B >= nbox) return;
+  // equal work per task (P2P^T: the box's own panels times the targets)
+  if (per_source) chunk = task_chunk(chunk, b.end[B] - b.start[B], kMinChunk, kMaxChunk);
   int nsub = 0, ntask = 0, cnt = 0, os = 0, ot = 0, firstsub = 0;
   if (FILL) {
     os = off_sub[B];
@@ -461,6 +481,32 @@ __global__ void k_source_slots(int N, const int *__restrict__ owner,
                                const int *__restrict__ count, int *__restrict__ tsl) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < N) tsl[i] = count[2 * owner[i] + 1] + 1;
+}
+
+
+// ---- moment tasks --------------------------------------------------------
+__global__ void k_need_moments(int n, const int *__restrict__ m2p_box, int *__restrict__ need) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) need[m2p_box[e]] = 1;  // every writer stores the same value
+}
+
+__global__ void k_mom_counts(int nbox, const int *__restrict__ need, Boxes b, int chunk,
+                             int *__restrict__ count) {
+  const int B = blockIdx.x * blockDim.x + threadIdx.x;
+  if (B < nbox) count[B] = need[B] ? (b.end[B] - b.start[B] + chunk - 1) / chunk : 0;
+}
+
+__global__ void k_mom_fill(int nbox, const int *__restrict__ first,
+                           const int *__restrict__ count, Boxes b, int chunk,
+                           int *__restrict__ task) {
+  const int B = blockIdx.x * blockDim.x + threadIdx.x;
+  if (B >= nbox) return;
+  for (int k = 0; k < count[B]; ++k) {
+    int *tk = task + 3 * (first[B] + k);
+    tk[0] = B;
+    tk[1] = b.start[B] + k * chunk;
+    tk[2] = min(b.end[B], b.start[B] + (k + 1) * chunk);
+  }
 }
 
 inline dim3 grid_for(size_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
@@ -561,14 +607,13 @@ void Tree::build_device(int N, int nf, const uint64_t *key, const double *geo,
     depth = l + 1;
     level_start.push_back(nbox);
   }
-  // leaves
-  Dbuf<int> bflag, bidx;
-  bflag.alloc(nbox);
-  bidx.alloc(nbox);
-  hipLaunchKernelGGL(k_leaf_flags, grid_for(nbox), dim3(256), 0, s, nbox, view(), bflag.p);
-  nleaf = exclusive_scan_total(s, bflag.p, bidx.p, nbox, tmp);
+  // leaves in key order: target leaves (and so tasks) that follow each
+  // other are neighbours in space, and the tasks that one XCD takes share
+  // their sources in its L2
+  hipLaunchKernelGGL(k_leaf_flags, grid_for(N), dim3(256), 0, s, N, owner.p, view(), flag.p);
+  nleaf = exclusive_scan_total(s, flag.p, idx.p, N, tmp);
   d_leaves.alloc(nleaf);
-  hipLaunchKernelGGL(k_leaf_list, grid_for(nbox), dim3(256), 0, s, nbox, bflag.p, bidx.p,
+  hipLaunchKernelGGL(k_leaf_list, grid_for(N), dim3(256), 0, s, N, flag.p, idx.p, owner.p,
                      d_leaves.p);
   d_range.alloc(2 * (size_t)nbox);
   d_child.alloc(8 * (size_t)nbox);
@@ -587,8 +632,8 @@ void Tree::build_device(int N, int nf, const uint64_t *key, const double *geo,
   ListOut lo{};
   lo.count = cnt.p;
   hipLaunchKernelGGL(k_lists<false>, grid_for(nleaf, 64), dim3(64), 0, s, nleaf, d_leaves.p,
-                     view(), d_center.p, d_radius.p, prm.theta, kP2PChunkPanels,
-                     kM2PChunkBoxes, lo);
+                     view(), d_center.p, d_radius.p, prm.theta, kP2PTaskWork,
+                     kM2PTaskWork, lo);
   PBMP_HIP(hipGetLastError());
   int tot[5];
   for (int c = 0; c < 5; ++c) {
@@ -625,8 +670,8 @@ void Tree::build_device(int N, int nf, const uint64_t *key, const double *geo,
   lo.mslot = d_m2p_slot.p;
   lo.slots_of_box = slots_of_box.p;
   hipLaunchKernelGGL(k_lists<true>, grid_for(nleaf, 64), dim3(64), 0, s, nleaf, d_leaves.p,
-                     view(), d_center.p, d_radius.p, prm.theta, kP2PChunkPanels,
-                     kM2PChunkBoxes, lo);
+                     view(), d_center.p, d_radius.p, prm.theta, kP2PTaskWork,
+                     kM2PTaskWork, lo);
   d_tslots.alloc(N);
   hipLaunchKernelGGL(k_target_slots, grid_for(N), dim3(256), 0, s, N, owner.p, slots_of_box.p,
                      d_tslots.p);
@@ -653,8 +698,28 @@ void Tree::build_device(int N, int nf, const uint64_t *key, const double *geo,
     m2p_pairs += (double)c[6] * c[0];
     max_slots = std::max(max_slots, c[3] + c[4]);
   }
+  // moment tasks for the boxes that some leaf accepts
+  {
+    Dbuf<int> need;
+    need.alloc(nbox);
+    hipLaunchKernelGGL(k_fill_int, grid_for(nbox), dim3(256), 0, s, nbox, 0, need.p);
+    if (n_m2p_entries > 0)
+      hipLaunchKernelGGL(k_need_moments, grid_for(n_m2p_entries), dim3(256), 0, s,
+                         n_m2p_entries, d_m2p_box.p, need.p);
+    d_mom_count.alloc(nbox);
+    d_mom_first.alloc(nbox);
+    hipLaunchKernelGGL(k_mom_counts, grid_for(nbox), dim3(256), 0, s, nbox, need.p, view(),
+                       kMomChunkPanels, d_mom_count.p);
+    n_mom_tasks = exclusive_scan_total(s, d_mom_count.p, d_mom_first.p, nbox, tmp);
+    d_mom_task.alloc(3 * (size_t)std::max(1, n_mom_tasks));
+    hipLaunchKernelGGL(k_mom_fill, grid_for(nbox), dim3(256), 0, s, nbox, d_mom_first.p,
+                       d_mom_count.p, view(), kMomChunkPanels, d_mom_task.p);
+    d_mom_part.alloc((size_t)std::max(1, n_mom_tasks) * 2 * ncoef);
+    PBMP_HIP(hipGetLastError());
+  }
   d_mom64.alloc((size_t)nbox * 2 * ncoef);
   d_mom32.alloc((size_t)nbox * 2 * ncoef);
+  PBMP_HIP(hipMemsetAsync(d_mom64.p, 0, sizeof(double) * nbox * 2 * ncoef, s));
   tree_upload_exponents(*this, s);
   PBMP_HIP(hipStreamSynchronize(s));
 }
@@ -664,7 +729,8 @@ void Tree::build_transposed(int N, const int *owner, Dbuf<char> &tmp) {
   auto view = [&]() {
     return Boxes{d_start.p, d_end.p, d_level.p, d_parent.p, d_first.p, d_nchild.p};
   };
-  auto one = [&](const Dbuf<int> &ptr, const Dbuf<int> &box, int n, int chunk, Dbuf<int> &tsub,
+  auto one = [&](const Dbuf<int> &ptr, const Dbuf<int> &box, int n, int chunk, bool per_source,
+                 Dbuf<int> &tsub,
                  Dbuf<int> &ttask, Dbuf<int> &cnt_out, Dbuf<int> &off_task, int &ntasks) {
     Dbuf<int> key, val, skey, sval, first, last, col, off_sub;
     const int m = std::max(1, n);
@@ -691,7 +757,8 @@ void Tree::build_transposed(int N, const int *owner, Dbuf<char> &tmp) {
     }
     cnt_out.alloc(2 * (size_t)nbox);
     hipLaunchKernelGGL(k_tasks_T<false>, grid_for(nbox, 64), dim3(64), 0, s, nbox, first.p,
-                       last.p, sval.p, d_leaves.p, view(), chunk, cnt_out.p, nullptr, nullptr,
+                       last.p, sval.p, d_leaves.p, view(), chunk, per_source, cnt_out.p, nullptr,
+                       nullptr,
                        nullptr, nullptr);
     col.alloc(nbox);
     off_sub.alloc(nbox);
@@ -703,15 +770,15 @@ void Tree::build_transposed(int N, const int *owner, Dbuf<char> &tmp) {
     tsub.alloc(2 * (size_t)std::max(1, nsub));
     ttask.alloc(4 * (size_t)std::max(1, ntasks));
     hipLaunchKernelGGL(k_tasks_T<true>, grid_for(nbox, 64), dim3(64), 0, s, nbox, first.p,
-                       last.p, sval.p, d_leaves.p, view(), chunk, nullptr, off_sub.p,
+                       last.p, sval.p, d_leaves.p, view(), chunk, per_source, nullptr, off_sub.p,
                        off_task.p, tsub.p, ttask.p);
     PBMP_HIP(hipGetLastError());
     PBMP_HIP(hipStreamSynchronize(s));
   };
   Dbuf<int> p2pT_off;
-  one(d_p2p_ptr, d_p2p_box, n_p2p_entries, kP2PChunkPanels, d_p2pT_sub, d_p2pT_task,
+  one(d_p2p_ptr, d_p2p_box, n_p2p_entries, kP2PTaskWork, true, d_p2pT_sub, d_p2pT_task,
       d_p2pT_count, p2pT_off, n_p2pT_tasks);
-  one(d_m2p_ptr, d_m2p_box, n_m2p_entries, kM2PTChunkTargets, d_m2pT_sub, d_m2pT_task,
+  one(d_m2p_ptr, d_m2p_box, n_m2p_entries, kM2PTChunkTargets, false, d_m2pT_sub, d_m2pT_task,
       d_m2pT_count, d_m2pT_off, n_m2pT_tasks);
   d_tslotsT.alloc(N);
   hipLaunchKernelGGL(k_source_slots, grid_for(N), dim3(256), 0, s, N, owner, d_p2pT_count.p,

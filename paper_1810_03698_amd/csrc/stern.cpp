@@ -112,14 +112,16 @@ void Runtime::apply_stern(const double *X, double *Y, bool f64) {
   const int N1 = N_, N2 = outer_->N_;
   apply(X, Y, f64);
   outer_->apply(X + 2 * (size_t)N1, Y + 2 * (size_t)N1, f64);
-  // G1 region-2 row: - (V21 q2 - K21 phi2) at G1
+  // G1 region-2 row: - (V21 q2 - K21 phi2) at G1 (the readout kernels
+  // return physical potentials, 4 pi times the integral-equation ones)
+  const double inv4pi = 1.0 / (4.0 * M_PI);
   outer_->probe(X + 2 * (size_t)N1, f64, outer_->pout_.p);
-  launch_add_strided(s_, N1, -1.0, outer_->pout_.p, 4, Y + N1);
+  launch_add_strided(s_, N1, -inv4pi, outer_->pout_.p, 4, Y + N1);
   // G2 region-2 row: + (V12 (e1/es) q1 - K12 phi1) at G2
   launch_scale(s_, N1, 1.0, X, sT_.p);
   launch_scale(s_, N1, o.eps_in / eps_stern_, X + N1, sT_.p + N1);
   probe(sT_.p, f64, pout_.p);
-  launch_add_strided(s_, N2, 1.0, pout_.p, 4, Y + 2 * (size_t)N1);
+  launch_add_strided(s_, N2, inv4pi, pout_.p, 4, Y + 2 * (size_t)N1);
 }
 
 void Runtime::precond_stern(const double *v, double *z) {

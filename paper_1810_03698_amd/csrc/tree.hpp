@@ -13,13 +13,19 @@ namespace pbmp {
 #define PBMP_M2P_CHUNK 16
 #endif
 constexpr int kM2PChunkBoxes = PBMP_M2P_CHUNK;
-// source panels per P2P task: a leaf's source list is cut at this size so
-// that no task is much longer than the others (the launch is short enough
-// for the longest task to set its duration)
-#ifndef PBMP_P2P_CHUNK
-#define PBMP_P2P_CHUNK 256
+// work per task, in target-source pairs: a leaf of nt targets gets tasks of
+// about kP2PTaskWork / nt source panels (P2P) and kM2PTaskWork / nt boxes
+// (M2P, at most kM2PChunkBoxes), so that tasks take about the same time
+#ifndef PBMP_P2P_WORK
+#define PBMP_P2P_WORK 16384
 #endif
-constexpr int kP2PChunkPanels = PBMP_P2P_CHUNK;
+#ifndef PBMP_M2P_WORK
+#define PBMP_M2P_WORK 1024
+#endif
+constexpr int kP2PTaskWork = PBMP_P2P_WORK;
+constexpr int kM2PTaskWork = PBMP_M2P_WORK;
+// panels per moment task
+constexpr int kMomChunkPanels = 2048;
 // target panels per M2P^T task (adjoint product)
 constexpr int kM2PTChunkTargets = 512;
 
@@ -64,6 +70,11 @@ class Tree {
   Dbuf<int> d_tslotsT;    // [N] transposed slots of the panel's leaf (tasks + 1)
   int n_p2pT_tasks = 0, n_m2pT_tasks = 0, max_slots_T = 1;
   Dbuf<double> d_Lpart, d_L;  // local coefficients: per M2P^T task, per box [2][ncoef]
+  // moment tasks: the panels of every accepted box in slices of at most
+  // kMomChunkPanels; task = (box, s0, s1); a box's slices are consecutive
+  int n_mom_tasks = 0;
+  Dbuf<int> d_mom_task, d_mom_first, d_mom_count;
+  Dbuf<double> d_mom_part;  // [n_mom_tasks][2][ncoef]
   Dbuf<double> d_mom64;   // [nbox][2][ncoef]
   Dbuf<float> d_mom32;    // [nbox][2][ncoef]
   Dbuf<int> d_monos;      // [3*ncoef] exponents

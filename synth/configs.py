@@ -126,7 +126,7 @@ WORKLOADS = {
 
 def workload(name, cache=True):
     """Return the named workload (see module docstring)."""
-    path = os.path.join(CACHE, name + ".npz")
+    path = os.path.join(CACHE, name + "_v2.npz")
     if cache and os.path.exists(path):
         z = np.load(path, allow_pickle=False)
         out = {k: z[k] for k in z.files if k != "params_keys"}

@@ -8,7 +8,8 @@ of gyration reaches the requested value.
 Surface: the isosurface rho(x) = 1 of the sum of Gaussians
     rho(x) = sum_a exp(-beta (|x - r_a|^2 / R_a^2 - 1)),   beta = 1,
 so an isolated atom's surface sits at its radius R_a.  It is triangulated by
-marching tetrahedra on a regular grid (each cube split into six tetrahedra
+marching tetrahedra on a regular grid, each crossing kept at least 0.2 of
+a grid step from the grid points (bounded triangle shapes) (each cube split into six tetrahedra
 around its main diagonal, identically in every cube, which makes the mesh
 watertight).  Interior voids are filled before meshing so the result is a
 single closed, outward-oriented surface.
@@ -186,7 +187,11 @@ def isosurface_mesh(rho, origin, h, iso=1.0):
     a, b = ukey // npts, ukey % npts
     unflat = lambda g: np.stack([g // (ny * nz), (g // nz) % ny, g % nz], 1)
     ra, rb = rho.ravel()[a], rho.ravel()[b]
-    t = (iso - ra) / (rb - ra)
+    # the crossing is kept within [0.2, 0.8] of its grid edge: vertices then
+    # never crowd a grid point, which would leave slivers of area ~1e-10 A^2
+    # and aspect ratios ~1e5; the surface moves by at most 0.2 h along
+    # the grid edges and stays closed (every vertex keeps its edge)
+    t = np.clip((iso - ra) / (rb - ra), 0.2, 0.8)
     pa = origin + h * unflat(a)
     pb = origin + h * unflat(b)
     verts = pa + t[:, None] * (pb - pa)

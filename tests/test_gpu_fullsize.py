@@ -140,17 +140,20 @@ def test_fullsize_energy_properties(name):
     """Mixed vs FP64 on the same method, and treecode vs direct."""
     w, m = _work(name)
     print(name, "mixed solve", flush=True)
-    rm = _solver(w).solve(outputs=False)
+    rm = _solver(w, gmres_maxit=4000).solve(outputs=False)
+    print(name, "status", rm["status"], "scf", rm["scf_iters"], "gmres", rm["gmres_iters"],
+          "relres", rm["relres"], flush=True)
     print(name, "fp64 solve", flush=True)
-    r64 = _solver(w, precision="fp64").solve(outputs=False)
+    r64 = _solver(w, precision="fp64", gmres_maxit=4000).solve(outputs=False)
+    print(name, "status", r64["status"], "scf", r64["scf_iters"], "gmres", r64["gmres_iters"],
+          "relres", r64["relres"], flush=True)
     rel = abs(rm["dG"] - r64["dG"]) / abs(r64["dG"])
-    print(name, "dG mixed", rm["dG"], "fp64", r64["dG"], "rel", rel,
-          "iters", rm["scf_iters"], rm["gmres_iters"], flush=True)
+    print(name, "dG mixed", rm["dG"], "fp64", r64["dG"], "rel", rel, flush=True)
     assert rm["status"] == 0 and r64["status"] == 0
     assert rel < 1e-4
     if w["params"]["mode"] == "treecode":
         print(name, "direct solve", flush=True)
-        rd = _solver(w, precision="mixed", mode="direct").solve(outputs=False)
+        rd = _solver(w, precision="mixed", mode="direct", gmres_maxit=4000).solve(outputs=False)
         rel_t = abs(r64["dG"] - rd["dG"]) / abs(rd["dG"])
         P = int(w["params"]["order_P"])
         print(name, "dG tree fp64", r64["dG"], "direct mixed", rd["dG"], "rel", rel_t)
