@@ -92,6 +92,11 @@ typedef struct pbmp_options {
   double thole_a;       /* Thole damping parameter, >= 0                    */
   int precision;        /* PBMP_FP64 or PBMP_MIXED                          */
   void *hip_stream;     /* hipStream_t to run on, or NULL                   */
+  int warm_start;       /* nonzero: a solve starts GMRES and both induced-
+                           dipole loops from the previous solve's surface
+                           solution and dipoles (same mesh and site count;
+                           sites may have moved), e.g. for nearby geometries
+                           in finite differences or dynamics; 0: from zero */
 } pbmp_options;
 
 typedef struct pbmp_ctx pbmp_ctx;
@@ -126,7 +131,8 @@ typedef struct pbmp_result {
 
 /* Fill `o` with defaults: eps 1/80, kappa 0.125, 3 far nodes, eta 2,
  * AUTO mode, theta 0.5, P 4, leaf 300, GMRES(50) tol 1e-6 maxit 1000,
- * SCF tol 1e-6 D, omega 0.7, maxit 200, Thole a 0.39, MIXED, NULL stream. */
+ * SCF tol 1e-6 D, omega 0.7, maxit 200, Thole a 0.39, MIXED, NULL stream,
+ * no warm start. */
 void pbmp_default_options(pbmp_options *o);
 
 /* Create a context on the current HIP device.  Validates the options

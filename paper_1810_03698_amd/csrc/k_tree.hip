@@ -64,12 +64,6 @@ template <int P> struct Multi {
 
 constexpr double kInv4PiT = 0.07957747154594767;
 
-// binomial coefficients C(a, b), a, b <= 6
-__constant__ double kBinom[7][7] = {
-    {1, 0, 0, 0, 0, 0, 0},   {1, 1, 0, 0, 0, 0, 0},    {1, 2, 1, 0, 0, 0, 0},
-    {1, 3, 3, 1, 0, 0, 0},   {1, 4, 6, 4, 1, 0, 0},    {1, 5, 10, 10, 5, 1, 0},
-    {1, 6, 15, 20, 15, 6, 1}};
-
 inline int ncoef_of(int P) { return (P + 1) * (P + 2) * (P + 3) / 6; }
 
 // blockIdx -> task: consecutive tasks (neighbouring target leaves, similar
@@ -534,9 +528,10 @@ void launch_moments(Tree &t, hipStream_t s, int nf, const double *src64) {
 // gathers, for every accepted box B, local coefficients
 //   L_B,k = sum over the targets i of the leaves that accepted B of z_i a_k(x_i - c_B)
 // (Laplace coefficients with the first component of z, Yukawa with the
-// second); L2L shifts them down the tree, (h + t)^k expanded as in M2M with
-// the roles transposed; L2P evaluates at every node y, h = y - c_leaf,
-//   V^T: sum_k L_k h^k,   K^T: n . grad_h sum_k L_k h^k.
+// second); L2P evaluates at every node y the expansions of all boxes that
+// contain it, h = y - c_B,
+//   V^T: sum_k L_k h^k,   K^T: n . grad_h sum_k L_k h^k,
+// the transpose of forming every box's moments from its nodes.
 
 template <class T, int NF, int SPT>
 __device__ void p2pT_body(const T *__restrict__ src, const T *__restrict__ tgt,
@@ -747,54 +742,18 @@ __global__ void k_l_reduce(int nbox, int ncoef2, const int *__restrict__ count,
   Lb[e] = v;
 }
 
-// L2L for the boxes of one level: each child adds its parent's expansion
-// re-centred, L_C,j += sum_{k >= j} C(k, j) t^{k-j} L_B,k, t = c_C - c_B
-template <int P>
-__global__ __launch_bounds__(64) void k_l2l(int base, const int *__restrict__ child,
-                                            const double *__restrict__ center,
-                                            double *__restrict__ Lb) {
-  constexpr Multi<P> mi{};
-  constexpr int NC = Multi<P>::n;
-  __shared__ double tp[3][P + 1];
-  __shared__ double lp[2 * NC];
-  const int B = base + (int)blockIdx.x;
-  if (child[8 * B] < 0) return;  // a leaf (uniform per block)
-  for (int k = threadIdx.x; k < 2 * NC; k += 64) lp[k] = Lb[(size_t)B * 2 * NC + k];
-  for (int cc = 0; cc < 8; ++cc) {
-    const int C = child[8 * B + cc];
-    if (C < 0) break;
-    __syncthreads();
-    if (threadIdx.x < 3) {
-      const double t = center[3 * C + threadIdx.x] - center[3 * B + threadIdx.x];
-      double p = 1.0;
-      for (int e = 0; e <= P; ++e) {
-        tp[threadIdx.x][e] = p;
-        p *= t;
-      }
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j < NC; j += 64) {
-      const int jx = mi.e[j][0], jy = mi.e[j][1], jz = mi.e[j][2];
-      double vl = 0.0, vy = 0.0;
-      for (int kx = jx; kx <= P; ++kx)
-        for (int ky = jy; kx + ky <= P; ++ky)
-          for (int kz = jz; kx + ky + kz <= P; ++kz) {
-            const int k = Multi<P>::index(kx, ky, kz);
-            const double w = kBinom[kx][jx] * tp[0][kx - jx] * kBinom[ky][jy] *
-                             tp[1][ky - jy] * kBinom[kz][jz] * tp[2][kz - jz];
-            vl += w * lp[k];
-            vy += w * lp[NC + k];
-          }
-      Lb[(size_t)C * 2 * NC + j] += vl;
-      Lb[(size_t)C * 2 * NC + NC + j] += vy;
-    }
-  }
-}
+// L2P at the leaves: every node takes the local expansions of all boxes
+// on its leaf's path to the root, each about its own centre (the direct
+// counterpart of shifting them down level by level), lanes over the leaf's
+// panels, FP64.  Boxes that no leaf accepted carry zero coefficients and
+// are skipped.
+constexpr int kMaxChain = 24;
 
-// L2P at the leaves: lanes over the leaf's panels, FP64
 template <int P, int NF>
 __global__ __launch_bounds__(64) void k_l2p(const int *__restrict__ leaves,
                                             const int *__restrict__ range,
+                                            const int *__restrict__ parent,
+                                            const int *__restrict__ ntask,
                                             const double *__restrict__ center,
                                             const double *__restrict__ Lb,
                                             const double *__restrict__ src64,
@@ -803,34 +762,51 @@ __global__ __launch_bounds__(64) void k_l2p(const int *__restrict__ leaves,
                                             double *__restrict__ part) {
   constexpr Multi<P> mi{};
   constexpr int NC = Multi<P>::n;
-  __shared__ double lp[2 * NC];
+  __shared__ double lp[kMaxChain][2 * NC];
+  __shared__ double lc[kMaxChain][3];
+  __shared__ int chain[kMaxChain];
+  __shared__ int nchain;
   const int B = leaves[blockIdx.x];
-  for (int k = threadIdx.x; k < 2 * NC; k += 64) lp[k] = Lb[(size_t)B * 2 * NC + k];
+  if (threadIdx.x == 0) {
+    int n = 0;
+    for (int a = B; a >= 0 && n < kMaxChain; a = parent[a])
+      if (ntask[2 * a + 1] > 0) chain[n++] = a;
+    nchain = n;
+  }
   __syncthreads();
-  const double c[3] = {center[3 * B], center[3 * B + 1], center[3 * B + 2]};
+  const int nc = nchain;
+  for (int e = threadIdx.x; e < nc * 2 * NC; e += 64) {
+    const int a = e / (2 * NC), k = e % (2 * NC);
+    lp[a][k] = Lb[(size_t)chain[a] * 2 * NC + k];
+  }
+  for (int e = threadIdx.x; e < nc * 3; e += 64) lc[e / 3][e % 3] = center[3 * chain[e / 3] + e % 3];
+  __syncthreads();
   for (int j = range[2 * B] + (int)threadIdx.x; j < range[2 * B + 1]; j += 64) {
     const double *r = src64 + 16 * (size_t)j;
     const double n[3] = {r[9], r[10], r[11]};
     double out[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int q = 0; q < NF; ++q) {
-      const double h[3] = {r[3 * q] - c[0], r[3 * q + 1] - c[1], r[3 * q + 2] - c[2]};
-      double mono[NC];
-      mono[0] = 1.0;
+    for (int a = 0; a < nc; ++a) {
+      for (int q = 0; q < NF; ++q) {
+        const double h[3] = {r[3 * q] - lc[a][0], r[3 * q + 1] - lc[a][1],
+                             r[3 * q + 2] - lc[a][2]};
+        double mono[NC];
+        mono[0] = 1.0;
 #pragma unroll
-      for (int k = 1; k < NC; ++k) {
-        const int d = mi.e[k][0] ? 0 : (mi.e[k][1] ? 1 : 2);
-        mono[k] = mono[mi.m1[k][d]] * h[d];
-      }
+        for (int k = 1; k < NC; ++k) {
+          const int d = mi.e[k][0] ? 0 : (mi.e[k][1] ? 1 : 2);
+          mono[k] = mono[mi.m1[k][d]] * h[d];
+        }
 #pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        double dn = 0.0;
+        for (int k = 0; k < NC; ++k) {
+          double dn = 0.0;
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
-          if (mi.m1[k][d] >= 0) dn += mi.e[k][d] * n[d] * mono[mi.m1[k][d]];
-        out[0] += lp[k] * mono[k];
-        out[1] += lp[k] * dn;
-        out[2] += lp[NC + k] * mono[k];
-        out[3] += lp[NC + k] * dn;
+          for (int d = 0; d < 3; ++d)
+            if (mi.m1[k][d] >= 0) dn += mi.e[k][d] * n[d] * mono[mi.m1[k][d]];
+          out[0] += lp[a][k] * mono[k];
+          out[1] += lp[a][k] * dn;
+          out[2] += lp[a][NC + k] * mono[k];
+          out[3] += lp[a][NC + k] * dn;
+        }
       }
     }
     const double wA = geo[6 * (size_t)N + j] * kInv4PiT / NF;
@@ -894,18 +870,14 @@ void tree_T_far(Tree &t, hipStream_t s, int nf, int N, const double *geo,
   const int nl = t.nbox * 2 * NC;
   hipLaunchKernelGGL(k_l_reduce, dim3((nl + 255) / 256), dim3(256), 0, s, t.nbox, 2 * NC,
                      t.d_m2pT_count.p, t.d_m2pT_off.p, t.d_Lpart.p, t.d_L.p);
-  for (int l = 0; l < t.depth; ++l) {
-    const int nb = t.level_start[l + 1] - t.level_start[l];
-    if (nb > 0)
-      hipLaunchKernelGGL(k_l2l<P>, dim3(nb), dim3(64), 0, s, t.level_start[l], t.d_child.p,
-                         t.d_center.p, t.d_L.p);
-  }
   if (nf == 3)
     hipLaunchKernelGGL((k_l2p<P, 3>), dim3(t.nleaf), dim3(64), 0, s, t.d_leaves.p,
-                       t.d_range.p, t.d_center.p, t.d_L.p, src64, geo, t.d_tslotsT.p, N, part);
+                       t.d_range.p, t.d_parent.p, t.d_m2pT_count.p, t.d_center.p, t.d_L.p,
+                       src64, geo, t.d_tslotsT.p, N, part);
   else
     hipLaunchKernelGGL((k_l2p<P, 1>), dim3(t.nleaf), dim3(64), 0, s, t.d_leaves.p,
-                       t.d_range.p, t.d_center.p, t.d_L.p, src64, geo, t.d_tslotsT.p, N, part);
+                       t.d_range.p, t.d_parent.p, t.d_m2pT_count.p, t.d_center.p, t.d_L.p,
+                       src64, geo, t.d_tslotsT.p, N, part);
   PBMP_HIP(hipGetLastError());
 }
 

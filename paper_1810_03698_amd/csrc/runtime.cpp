@@ -273,6 +273,7 @@ void Runtime::set_mesh(int64_t nv, const double *verts, int64_t nt,
     for (int k = 0; k < 3; ++k) h_tri_[3 * i + k] = ht[3 * perm_[i] + k];
   N_ = N;
   Nv_ = Nv;
+  warm_ok_ = false;
   h_verts_ = hv;
   solved_ = false;
   M_ = 0;
@@ -452,6 +453,7 @@ void Runtime::set_sites(int64_t m, const double *xyz, const double *q,
       PBMP_REQUIRE(dx * dx + dy * dy + dz * dz > 0, PBMP_EARG, "coincident sites");
       if (M > 4096) break;  // pairwise check only for small inputs
     }
+  if (M != M_) warm_ok_ = false;
   M_ = M;
   h_sxyz_ = hx;
   sxyz_.upload(hx.data(), hx.size(), s_);
@@ -791,12 +793,16 @@ void Runtime::readout(const double *x, bool full, double *out) {
 int Runtime::scf(bool solvent, double *mu, int *gm_warn) {
   const int M = M_, N = N_;
   const double dbye = debye_per_e_ang();
-  PBMP_HIP(hipMemsetAsync(mu, 0, sizeof(double) * 3 * M, s_));
+  // warm start: keep the previous solve's dipoles and surface solution
+  const bool warm = o.warm_start && warm_ok_;
+  if (!warm) PBMP_HIP(hipMemsetAsync(mu, 0, sizeof(double) * 3 * M, s_));
   launch_perm_field(s_, M, sxyz_.p, sq_.p, sd_.p, sQ_.p, sgroup_.p, o.eps_in, Eperm_.p);
   if (solvent) {
-    PBMP_HIP(hipMemsetAsync(x_.p, 0, sizeof(double) * 2 * N, s_));
     PBMP_HIP(hipMemsetAsync(b_.p, 0, sizeof(double) * 2 * N, s_));
-    if (outer_) PBMP_HIP(hipMemsetAsync(sX_.p, 0, sizeof(double) * sX_.n, s_));
+    if (!warm) {
+      PBMP_HIP(hipMemsetAsync(x_.p, 0, sizeof(double) * 2 * N, s_));
+      if (outer_) PBMP_HIP(hipMemsetAsync(sX_.p, 0, sizeof(double) * sX_.n, s_));
+    }
   }
   for (int it = 1; it <= o.scf_maxit; ++it) {
     if (solvent) {
@@ -855,6 +861,7 @@ int Runtime::solve(pbmp_result *r) {
   r->dG_pol_kcal = C * e[1];
   r->dG_kcal = C * (e[0] + e[1]);
   r->G_vac_kcal = C * (e[2] + e[3]);
+  warm_ok_ = true;
   r->scf_iters = std::abs(it_d);
   r->scf_iters_vac = std::abs(it_v);
   r->gmres_iters_total = gmres_iters_;

@@ -109,6 +109,7 @@ class Runtime {
   Dbuf<double> io_a_, io_b_;  // permutation staging
   Dbuf<double> vac_perm_, vac_ind_;  // vacuum-state potential data [10M]
   bool solved_ = false;
+  bool warm_ok_ = false;  // x_, mu_d_, mu_v_ hold a previous solve of this mesh and site count
   int gmres_iters_ = 0, matvecs_ = 0;
   double last_relres_ = 0.0;
   double t_matvec_ms_ = 0.0;

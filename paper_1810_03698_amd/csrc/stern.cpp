@@ -55,6 +55,7 @@ void Runtime::set_stern(int64_t nv, const double *verts, int64_t nt, const int32
       outer_.reset();
       build_near_lists();
     }
+    warm_ok_ = false;
     solved_ = false;
     return;
   }
@@ -104,6 +105,7 @@ void Runtime::set_stern(int64_t nv, const double *verts, int64_t nt, const int32
   sB_.alloc(n);
   sY_.alloc(n);
   sT_.alloc(2 * (size_t)N1);
+  warm_ok_ = false;
   partial_.reserve((size_t)(o.gmres_restart + 2) * ((n + 4095) / 4096 + 1));
   solved_ = false;
 }

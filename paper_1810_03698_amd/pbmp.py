@@ -32,7 +32,8 @@ class Options(ctypes.Structure):
                 ("gmres_tol", ctypes.c_double), ("gmres_maxit", ctypes.c_int),
                 ("scf_tol_debye", ctypes.c_double), ("scf_omega", ctypes.c_double),
                 ("scf_maxit", ctypes.c_int), ("thole_a", ctypes.c_double),
-                ("precision", ctypes.c_int), ("hip_stream", ctypes.c_void_p)]
+                ("precision", ctypes.c_int), ("hip_stream", ctypes.c_void_p),
+                ("warm_start", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
@@ -165,7 +166,8 @@ class Solver:
                  near_eta=2.0, mode="auto", theta=0.5, order_P=4,
                  leaf_panels=300, gmres_restart=50, gmres_tol=1e-6,
                  gmres_maxit=1000, scf_tol_debye=1e-6, scf_omega=0.7,
-                 scf_maxit=200, thole_a=0.39, precision="mixed", stream=None):
+                 scf_maxit=200, thole_a=0.39, precision="mixed", stream=None,
+                 warm_start=False):
         self.lib = load()
         o = Options()
         self.lib.pbmp_default_options(ctypes.byref(o))
@@ -178,6 +180,7 @@ class Solver:
         o.thole_a = thole_a
         o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
         o.hip_stream = stream
+        o.warm_start = int(bool(warm_start))
         self.opts = o
         ctx = ctypes.c_void_p()
         rc = self.lib.pbmp_create(ctypes.byref(o), ctypes.byref(ctx))

@@ -158,3 +158,44 @@ def test_fullsize_energy_properties(name):
         P = int(w["params"]["order_P"])
         print(name, "dG tree fp64", r64["dG"], "direct mixed", rd["dG"], "rel", rel_t)
         assert rel_t < (2e-5 if P <= 4 else 1e-5) + 1e-6
+
+
+def test_fullsize_gradients_fd_globule_5000():
+    """The 5000-atom globule (treecode, P = 5): adjoint gradients of the
+    solvation energy for 20 seeded atoms against central differences
+    (h = 1e-4 A) along a random direction per atom, each displaced solve
+    warm-started from the base solution (FP64 throughout, tight
+    tolerances)."""
+    from paper_1810_03698_amd import Solver
+    w, m = _work("globule_5000")
+    p = w["params"]
+    kw = dict(precision="fp64", gmres_tol=1e-11, scf_tol_debye=1e-10, gmres_maxit=6000,
+              scf_maxit=500, warm_start=True)
+    s = _solver(w, **kw)
+    print("base solve", flush=True)
+    base = s.solve(outputs=False)
+    print("base", base["dG"], base["status"], base["scf_iters"], base["gmres_iters"], flush=True)
+    g = s.backward(1.0, verts=False)
+    rng = np.random.default_rng(20)
+    atoms = np.sort(rng.choice(len(w["q"]), 20, replace=False))
+    h = 1e-4
+    gmax = np.abs(g["xyz"]).max()
+    worst = 0.0
+    for l in atoms:
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        e = []
+        for sign in (1.0, -1.0):
+            xyz = w["xyz"].copy()
+            xyz[l] += sign * h * u
+            s.set_sites(xyz, w["q"], w["d"], w["Q9"], w["alpha"])
+            r = s.solve(outputs=False)
+            assert r["status"] == 0
+            e.append(r["dG"])
+        fd = (e[0] - e[1]) / (2 * h)
+        an = g["xyz"][l] @ u
+        err = abs(an - fd) / max(abs(fd), 1e-2 * gmax)
+        worst = max(worst, err)
+        print("atom", l, "adjoint", an, "fd", fd, "rel", err, flush=True)
+    s.close()
+    assert worst < 1e-4
