@@ -30,7 +30,12 @@ COPY_BYTES = 256 << 20
 # (FETCH_SIZE reads 0.5004 of the bytes read, WRITE_SIZE 1.0 of the bytes
 # written).  Keyed by (mode, kernel); valid only while the sources of the
 # kernel hash to the recorded value (otherwise traffic is reported null).
-TRAFFIC = {}
+TRAFFIC = {
+    ("treecode", "p2p"): {"fetch_kib": 5637.33, "fetch_scale": 0.50006,
+                          "write_kib": 39114.76, "write_scale": 1.0, "sha": "f5ce7de506bccbda"},
+    ("direct", "p2p"): {"fetch_kib": 20980.51, "fetch_scale": 0.50008,
+                        "write_kib": 33280.0, "write_scale": 1.0, "sha": "693f91615dd1aabb"},
+}
 TRAFFIC_SOURCES = {
     ("treecode", "p2p"): ["k_tree.hip", "pair.hpp", "tree.hpp", "k_treebuild.hip"],
     ("direct", "p2p"): ["k_p2p.hip", "pair.hpp"],

@@ -139,6 +139,13 @@ void pbmp_default_options(pbmp_options *o);
  * (PBMP_EARG on a value out of range).  *out receives the context. */
 int pbmp_create(const pbmp_options *o, pbmp_ctx **out);
 
+/* Change the solver settings of an existing context between solves:
+ * gmres_restart, gmres_tol, gmres_maxit, scf_tol_debye, scf_omega,
+ * scf_maxit and warm_start are taken from *o (range-checked as in
+ * pbmp_create); every other field must equal the context's (PBMP_EARG
+ * otherwise: the discretisation is fixed at creation). */
+int pbmp_set_options(pbmp_ctx *c, const pbmp_options *o);
+
 /* Set the surface mesh: nv vertices [nv*3] (x,y,z per vertex, row-major),
  * nt triangles [nt*3] of vertex indices, counter-clockwise seen from the
  * solvent (section "The boundary integral formulation": n points out of the

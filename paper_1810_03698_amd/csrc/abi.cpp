@@ -144,6 +144,14 @@ int pbmp_kernel_stats(pbmp_ctx *c, int mode, pbmp_kstats *out) {
   });
 }
 
+int pbmp_set_options(pbmp_ctx *c, const pbmp_options *o) {
+  return guarded(c, [&] {
+    PBMP_REQUIRE(o != nullptr, PBMP_EARG, "null options");
+    c->rt->set_options(*o);
+    return 0;
+  });
+}
+
 int pbmp_set_stern(pbmp_ctx *c, int64_t nv, const double *verts, int64_t nt,
                    const int32_t *tris, double eps_stern, int where) {
   return guarded(c, [&] {

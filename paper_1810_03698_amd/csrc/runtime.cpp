@@ -204,6 +204,42 @@ Runtime::Runtime(const pbmp_options &opt) : o(opt) {
   gauss_legendre(16, ru_.glx, ru_.glw);
 }
 
+void Runtime::set_options(const pbmp_options &n) {
+  const double kap = outer_ ? kappa_ext_ : o.kappa;
+  const double eout = outer_ ? eps_out_ext_ : o.eps_out;
+  PBMP_REQUIRE(n.eps_in == o.eps_in && n.eps_out == eout && n.kappa == kap &&
+                   n.gauss_far == o.gauss_far && n.near_eta == o.near_eta &&
+                   n.mode == o.mode && n.theta == o.theta && n.order_P == o.order_P &&
+                   n.leaf_panels == o.leaf_panels && n.thole_a == o.thole_a &&
+                   n.precision == o.precision,
+               PBMP_EARG, "only the solver settings can change on a context");
+  PBMP_REQUIRE(n.gmres_restart >= 1 && n.gmres_restart <= 200, PBMP_EARG,
+               "gmres_restart in 1..200");
+  PBMP_REQUIRE(n.gmres_tol > 0 && n.gmres_maxit >= 1, PBMP_EARG,
+               "gmres_tol > 0, gmres_maxit >= 1");
+  PBMP_REQUIRE(n.scf_tol_debye > 0 && n.scf_maxit >= 1, PBMP_EARG,
+               "scf_tol_debye > 0, scf_maxit >= 1");
+  PBMP_REQUIRE(n.scf_omega > 0 && n.scf_omega < 2, PBMP_EARG, "scf_omega in (0,2)");
+  const bool restart_changed = n.gmres_restart != o.gmres_restart;
+  o.gmres_restart = n.gmres_restart;
+  o.gmres_tol = n.gmres_tol;
+  o.gmres_maxit = n.gmres_maxit;
+  o.scf_tol_debye = n.scf_tol_debye;
+  o.scf_omega = n.scf_omega;
+  o.scf_maxit = n.scf_maxit;
+  o.warm_start = n.warm_start;
+  if (outer_) {
+    outer_->o.gmres_restart = n.gmres_restart;
+    outer_->o.gmres_tol = n.gmres_tol;
+    outer_->o.gmres_maxit = n.gmres_maxit;
+  }
+  if (restart_changed && N_ > 0) {
+    alloc_work();
+    if (outer_)
+      partial_.reserve((size_t)(o.gmres_restart + 2) * ((sX_.n + 4095) / 4096 + 1));
+  }
+}
+
 Runtime::~Runtime() {
   try {
     clock.resolve();

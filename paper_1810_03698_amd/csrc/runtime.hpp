@@ -56,6 +56,8 @@ class Runtime {
                    double *box_centre, double *box_radius, int32_t *leaf_box,
                    int32_t *m2p_ptr, int32_t *m2p_box, int32_t *p2p_ptr,
                    int32_t *p2p_box) const;
+  // solver settings between solves (discretisation fields must not change)
+  void set_options(const pbmp_options &n);
   // ion-exclusion layer: outer surface G2 and its permittivity (nt = 0 removes it)
   void set_stern(int64_t nv, const double *verts, int64_t nt, const int32_t *tris,
                  double eps_stern, int where);

@@ -62,7 +62,8 @@ _lib = None
 SYMBOLS = ["pbmp_default_options", "pbmp_create", "pbmp_set_mesh",
            "pbmp_set_sites", "pbmp_solve", "pbmp_matvec", "pbmp_rhs",
            "pbmp_site_fields", "pbmp_backward", "pbmp_last_error",
-           "pbmp_destroy", "pbmp_kernel_stats", "pbmp_tree_export", "pbmp_set_stern"]
+           "pbmp_destroy", "pbmp_kernel_stats", "pbmp_tree_export", "pbmp_set_stern",
+           "pbmp_set_options"]
 
 
 def _torch_runtime_first():
@@ -105,9 +106,11 @@ def load():
     lib.pbmp_kernel_stats.argtypes = [P, I, ctypes.POINTER(KernelStats)]
     lib.pbmp_tree_export.argtypes = [P] * 12
     lib.pbmp_set_stern.argtypes = [P, L, P, L, P, D, I]
+    lib.pbmp_set_options.argtypes = [P, ctypes.POINTER(Options)]
     for name in ("pbmp_create", "pbmp_set_mesh", "pbmp_set_sites", "pbmp_solve",
                  "pbmp_matvec", "pbmp_rhs", "pbmp_site_fields", "pbmp_backward",
-                 "pbmp_kernel_stats", "pbmp_tree_export", "pbmp_set_stern"):
+                 "pbmp_kernel_stats", "pbmp_tree_export", "pbmp_set_stern",
+                 "pbmp_set_options"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -212,6 +215,18 @@ class Solver:
         self._check(self.lib.pbmp_set_mesh(self.ctx, nv, v.ptr, nt, t.ptr,
                                            _common_where([v, t])))
         self.nt, self.nv, self.nt2 = nt, nv, 0
+
+    def set_options(self, **kw):
+        """Change solver settings between solves (gmres_restart, gmres_tol,
+        gmres_maxit, scf_tol_debye, scf_omega, scf_maxit, warm_start)."""
+        o = self.opts
+        for k, v in kw.items():
+            if k not in ("gmres_restart", "gmres_tol", "gmres_maxit", "scf_tol_debye",
+                         "scf_omega", "scf_maxit", "warm_start"):
+                raise ValueError("%s is fixed at creation" % k)
+            setattr(o, k, int(v) if k in ("gmres_restart", "gmres_maxit", "scf_maxit",
+                                          "warm_start") else float(v))
+        self._check(self.lib.pbmp_set_options(self.ctx, ctypes.byref(o)))
 
     def set_stern(self, verts, tris, eps_stern):
         """Enclosing ion-exclusion surface (see pbmp_set_stern); tris=None

@@ -140,11 +140,11 @@ def test_fullsize_energy_properties(name):
     """Mixed vs FP64 on the same method, and treecode vs direct."""
     w, m = _work(name)
     print(name, "mixed solve", flush=True)
-    rm = _solver(w, gmres_maxit=4000).solve(outputs=False)
+    rm = _solver(w, gmres_restart=100, gmres_maxit=8000).solve(outputs=False)
     print(name, "status", rm["status"], "scf", rm["scf_iters"], "gmres", rm["gmres_iters"],
           "relres", rm["relres"], flush=True)
     print(name, "fp64 solve", flush=True)
-    r64 = _solver(w, precision="fp64", gmres_maxit=4000).solve(outputs=False)
+    r64 = _solver(w, precision="fp64", gmres_restart=100, gmres_maxit=8000).solve(outputs=False)
     print(name, "status", r64["status"], "scf", r64["scf_iters"], "gmres", r64["gmres_iters"],
           "relres", r64["relres"], flush=True)
     rel = abs(rm["dG"] - r64["dG"]) / abs(r64["dG"])
@@ -153,7 +153,8 @@ def test_fullsize_energy_properties(name):
     assert rel < 1e-4
     if w["params"]["mode"] == "treecode":
         print(name, "direct solve", flush=True)
-        rd = _solver(w, precision="mixed", mode="direct", gmres_maxit=4000).solve(outputs=False)
+        rd = _solver(w, precision="mixed", mode="direct", gmres_restart=100,
+                     gmres_maxit=8000).solve(outputs=False)
         rel_t = abs(r64["dG"] - rd["dG"]) / abs(rd["dG"])
         P = int(w["params"]["order_P"])
         print(name, "dG tree fp64", r64["dG"], "direct mixed", rd["dG"], "rel", rel_t)
@@ -163,19 +164,21 @@ def test_fullsize_energy_properties(name):
 def test_fullsize_gradients_fd_globule_5000():
     """The 5000-atom globule (treecode, P = 5): adjoint gradients of the
     solvation energy for 20 seeded atoms against central differences
-    (h = 1e-4 A) along a random direction per atom, each displaced solve
-    warm-started from the base solution (FP64 throughout, tight
-    tolerances)."""
-    from paper_1810_03698_amd import Solver
+    (h = 1e-4 A) along a random direction per atom.  FP64 throughout; the
+    base state is solved in stages of tightening tolerance (each warm-started
+    from the last), and every displaced solve is warm-started from the base
+    solution."""
     w, m = _work("globule_5000")
-    p = w["params"]
-    kw = dict(precision="fp64", gmres_tol=1e-11, scf_tol_debye=1e-10, gmres_maxit=6000,
-              scf_maxit=500, warm_start=True)
-    s = _solver(w, **kw)
-    print("base solve", flush=True)
-    base = s.solve(outputs=False)
-    print("base", base["dG"], base["status"], base["scf_iters"], base["gmres_iters"], flush=True)
+    s = _solver(w, precision="fp64", gmres_restart=100, gmres_maxit=20000, scf_maxit=500,
+                warm_start=True)
+    for gtol, stol in ((1e-6, 1e-6), (1e-9, 1e-8), (1e-12, 1e-11)):
+        s.set_options(gmres_tol=gtol, scf_tol_debye=stol)
+        base = s.solve(outputs=False)
+        print("base stage", gtol, base["dG"], base["status"], base["scf_iters"],
+              base["gmres_iters"], flush=True)
+        assert base["status"] == 0
     g = s.backward(1.0, verts=False)
+    print("backward done", flush=True)
     rng = np.random.default_rng(20)
     atoms = np.sort(rng.choice(len(w["q"]), 20, replace=False))
     h = 1e-4
