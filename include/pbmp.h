@@ -127,6 +127,11 @@ typedef struct pbmp_result {
                               vacuum induced dipoles (eq. energy_multipole_
                               polarizable); G_AB - G_A - G_B of three solves
                               is the vacuum binding energy (eq. bind_vac)  */
+  double dipole_vac_debye[3];  /* total dipole of the molecule, vacuum state:
+                                  sum of q (r - o) + d + mu_vac over sites,
+                                  o = mean site position, Debye (the
+                                  diagnostic of Table "dipole")           */
+  double dipole_diss_debye[3]; /* the same with mu_diss (dissolved state)  */
 } pbmp_result;
 
 /* Fill `o` with defaults: eps 1/80, kappa 0.125, 3 far nodes, eta 2,
@@ -199,12 +204,17 @@ int pbmp_site_fields(pbmp_ctx *c, const double *x, double *out, int where);
  * GMRES on the transposed operator, and the explicit derivatives of every
  * pair term (operator entries including near-singular and singular panels,
  * right-hand side, readout, Coulomb and Thole interactions).  Near/far
- * decisions and lists are held fixed.  Needs a successful pbmp_solve with
+ * decisions and lists are held fixed.  The transposed solves use the
+ * context's GMRES tolerance and the transposed loops stop at a relative
+ * change of a tenth of it (clamped to [1e-11, 1e-7]); pbmp_set_options may
+ * loosen it for the backward after a tight forward solve.  Needs a successful pbmp_solve with
  * unchanged inputs (PBMP_ESTATE otherwise).  Any output may be NULL
- * (skipped).  In treecode mode the adjoint products are direct (O(nt^2)), so
- * the gradient is that of the direct-operator energy at the treecode
- * solution (agreement to the treecode's accuracy).  Returns +1/+2 when an
- * adjoint solve did not converge. */
+ * (skipped).  In treecode mode the transposed solves use the exact
+ * transpose of the treecode product, so site gradients are those of the
+ * treecode energy; the operator's dependence on the vertices is
+ * differentiated directly (O(nt^2)), so vertex gradients are those of the
+ * direct operator at the treecode solution (agreement to the treecode's
+ * accuracy).  Returns +1/+2 when an adjoint solve did not converge. */
 int pbmp_backward(pbmp_ctx *c, double dG_bar, double *g_xyz, double *g_q,
                   double *g_d, double *g_Q9, double *g_verts, int where);
 

@@ -142,6 +142,19 @@ def vacuum_energy(xyz, q, d, Q9, alpha, mu_v, eps_in=1.0, thole_a=0.39):
     return mp.COULOMB_KCAL * 0.5 * _apply_D(q, d, Q9, perm + ind)
 
 
+def total_dipole(xyz, q, d, mu, origin=None):
+    """Total dipole moment of the molecule in Debye (the diagnostic of the
+    comparison with Tinker-APBS, Table "dipole"): sum over sites of
+    q_l (r_l - origin) + d_l + mu_l.  The paper names no origin; here it is
+    the unweighted mean of the site positions (for a neutral molecule the
+    result does not depend on it)."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    o = xyz.mean(axis=0) if origin is None else np.asarray(origin, dtype=np.float64)
+    p = (np.asarray(q)[:, None] * (xyz - o)).sum(axis=0) + np.asarray(d).sum(axis=0) \
+        + np.asarray(mu).sum(axis=0)
+    return p * mp.DEBYE_PER_EA
+
+
 def solvation(xyz, q, d, Q9, alpha, solvent, group=None, eps_in=1.0,
               thole_a=0.39, omega=0.7, tol_debye=1e-6, maxit=1000):
     """Full polarisable solvation energy.  Returns a dict with dG (kcal/mol),
@@ -163,6 +176,8 @@ def solvation(xyz, q, d, Q9, alpha, solvent, group=None, eps_in=1.0,
     e_pol = 0.5 * _apply_D(q, d, Q9, ind_d - ind_v)
     dG = mp.COULOMB_KCAL * (e_solv + e_pol)
     return dict(dG=dG, G_vac=vacuum_energy(xyz, q, d, Q9, alpha, mu_v, eps_in, thole_a),
+                dipole_vac=total_dipole(xyz, q, d, mu_v),
+                dipole_diss=total_dipole(xyz, q, d, mu_d),
                 mu_diss=mu_d, mu_vac=mu_v, scf_iters=it_d,
                 scf_iters_vac=it_v, reaction=reac,
                 x=getattr(solvent, "x", None),

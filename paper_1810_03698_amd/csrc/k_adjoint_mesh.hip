@@ -10,6 +10,7 @@
 
 #include "dual.hpp"
 #include "kernels.hpp"
+#include "pair.hpp"
 #include "panel.hpp"
 
 namespace pbmp {
@@ -28,6 +29,10 @@ __device__ inline double op_pair(const double R[3], const double n[3], double ka
                                  double a1, double a2, double a3, double a4, double gR[3],
                                  double gn[3]) {
   const double rr = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+  if (rr < kMinR2d) {  // a node on the target (one-node rule, self panel): no term
+    for (int d = 0; d < 3; ++d) gR[d] = gn[d] = 0.0;
+    return 0.0;
+  }
   const double r = sqrt(rr);
   const double ri = 1.0 / r, ri3 = ri / rr, ri5 = ri3 / rr;
   const double e = exp(-kappa * r);

@@ -379,7 +379,53 @@ __global__ void k_energy(int M, const double *__restrict__ q,
   }
 }
 
+// Total dipole of the molecule for the vacuum and dissolved dipoles:
+// sum_l q_l (r_l - o) + d_l + mu_l with o the mean site position, e*A.
+__global__ void k_total_dipole(int M, const double *__restrict__ xyz,
+                               const double *__restrict__ q,
+                               const double *__restrict__ d,
+                               const double *__restrict__ mu_v,
+                               const double *__restrict__ mu_d,
+                               double *__restrict__ out) {
+  constexpr int K = 13;  // sum q, sum q r, sum r, sum (d + mu_v), sum mu_d - mu_v
+  __shared__ double red[K][256];
+  double a[K];
+  for (int k = 0; k < K; ++k) a[k] = 0.0;
+  for (int l = threadIdx.x; l < M; l += blockDim.x) {
+    const double ql = q[l];
+    a[0] += ql;
+    for (int c = 0; c < 3; ++c) {
+      const double r = xyz[3 * l + c];
+      a[1 + c] += ql * r;
+      a[4 + c] += r;
+      a[7 + c] += d[3 * l + c] + mu_v[3 * l + c];
+      a[10 + c] += mu_d[3 * l + c] - mu_v[3 * l + c];
+    }
+  }
+  for (int k = 0; k < K; ++k) red[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int k = 0; k < K; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) {
+    const int c = threadIdx.x;
+    const double pv = red[1 + c][0] - red[0][0] * red[4 + c][0] / M + red[7 + c][0];
+    out[c] = pv;
+    out[3 + c] = pv + red[10 + c][0];
+  }
+}
+
 }  // namespace
+
+void launch_total_dipole(hipStream_t s, int M, const double *xyz, const double *q,
+                         const double *d, const double *mu_v, const double *mu_d,
+                         double *out) {
+  hipLaunchKernelGGL(k_total_dipole, dim3(1), dim3(256), 0, s, M, xyz, q, d, mu_v,
+                     mu_d, out);
+  PBMP_HIP(hipGetLastError());
+}
 
 void launch_rhs(hipStream_t s, bool fp64, int N, int M, const double *geo,
                 const double *xyz, const double *q, const double *p,

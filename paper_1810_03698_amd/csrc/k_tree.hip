@@ -85,14 +85,20 @@ __device__ inline int xcd_task(int ntasks) {
 // adds a box's slices in a fixed order.  Computing every level from the
 // nodes replaces the upward shifts (M2M) with one launch and no
 // accumulated shift rounding.
+#ifndef PBMP_P2M_THREADS
+#define PBMP_P2M_THREADS 256
+#endif
+constexpr int kP2MThreads = PBMP_P2M_THREADS;
+
 template <int P>
-__global__ __launch_bounds__(256) void k_p2m_tasks(int nf, const int *__restrict__ tasks,
+__global__ __launch_bounds__(kP2MThreads) void k_p2m_tasks(int nf, const int *__restrict__ tasks,
                                                    const double *__restrict__ center,
                                                    const double *__restrict__ src,
                                                    double *__restrict__ part) {
   constexpr Multi<P> mi{};
   constexpr int NC = Multi<P>::n;
-  __shared__ double red[4][2 * NC];
+  constexpr int NW = kP2MThreads / 64;
+  __shared__ double red[NW][2 * NC];
   const int B = tasks[3 * blockIdx.x];
   const int s0 = tasks[3 * blockIdx.x + 1], s1 = tasks[3 * blockIdx.x + 2];
   const double c[3] = {center[3 * B], center[3 * B + 1], center[3 * B + 2]};
@@ -100,7 +106,7 @@ __global__ __launch_bounds__(256) void k_p2m_tasks(int nf, const int *__restrict
 #pragma unroll
   for (int k = 0; k < NC; ++k) m[k] = mk[k] = 0.0;
   const int nnode = (s1 - s0) * nf;
-  for (int g = threadIdx.x; g < nnode; g += 256) {
+  for (int g = threadIdx.x; g < nnode; g += kP2MThreads) {
     const int j = s0 + g / nf, q = g % nf;
     const double *r = src + 16 * (size_t)j;
     const double h[3] = {r[3 * q] - c[0], r[3 * q + 1] - c[1], r[3 * q + 2] - c[2]};
@@ -137,8 +143,11 @@ __global__ __launch_bounds__(256) void k_p2m_tasks(int nf, const int *__restrict
     }
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < 2 * NC; k += 256)
-    part[(size_t)blockIdx.x * 2 * NC + k] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+  for (int k = threadIdx.x; k < 2 * NC; k += kP2MThreads) {
+    double v = red[0][k];
+    for (int w = 1; w < NW; ++w) v += red[w][k];
+    part[(size_t)blockIdx.x * 2 * NC + k] = v;
+  }
 }
 
 // mom[B] = sum of the partial moments of B's slices, in slice order
@@ -502,8 +511,8 @@ void launch_m2p(Tree &t, hipStream_t s, const T *mom, const T *tgt, int N, T kap
 template <int P> void launch_moments_p(Tree &t, hipStream_t s, int nf, const double *src64) {
   constexpr int NC = Multi<P>::n;
   if (t.n_mom_tasks == 0) return;
-  hipLaunchKernelGGL(k_p2m_tasks<P>, dim3(t.n_mom_tasks), dim3(256), 0, s, nf, t.d_mom_task.p,
-                     t.d_center.p, src64, t.d_mom_part.p);
+  hipLaunchKernelGGL(k_p2m_tasks<P>, dim3(t.n_mom_tasks), dim3(kP2MThreads), 0, s, nf,
+                     t.d_mom_task.p, t.d_center.p, src64, t.d_mom_part.p);
   const int n = t.nbox * 2 * NC;
   hipLaunchKernelGGL(k_mom_reduce, dim3((n + 255) / 256), dim3(256), 0, s, t.nbox, 2 * NC,
                      t.d_mom_first.p, t.d_mom_count.p, t.d_mom_part.p, t.d_mom64.p);

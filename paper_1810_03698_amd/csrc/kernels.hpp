@@ -38,8 +38,9 @@ void launch_pack_strengths(hipStream_t s, int N, int nf, const double *geo,
 
 // Direct far-field sums over all panels of the source range, per target:
 // part[(chunk*4 + k)*Nt + i], k = V_L, K_L, V_Y, K_Y.
-// floor_r2: clamp FP32 distances at 1e-4 A (needed only when panels are
-// small enough for a node and a centroid to coincide in FP32).
+// floor_r2: FP32 pairs closer than 1e-4 A add nothing (needed only for the
+// one-node rule, or panels small enough for a node and a centroid to
+// coincide in FP32).
 void launch_p2p_direct(hipStream_t s, bool fp64, int nf, int N, int Nt,
                        const double *src64, const float *src32,
                        const double *geo, const float *tgt32, double kappa,
@@ -102,6 +103,11 @@ void launch_scf_update(hipStream_t s, int M, const double *alpha,
 // potential data [M,10] of the other sites' permanent multipoles (unmasked)
 void launch_perm_potential(hipStream_t s, int M, const double *xyz, const double *q,
                            const double *d, const double *Q, double eps_in, double *out);
+// Total molecular dipoles out[0..2] (vacuum) and out[3..5] (dissolved), e*A,
+// about the mean site position (one block).
+void launch_total_dipole(hipStream_t s, int M, const double *xyz, const double *q,
+                         const double *d, const double *mu_v, const double *mu_d,
+                         double *out);
 void launch_energy(hipStream_t s, int M, const double *q, const double *d,
                    const double *Q9, const double *reac10, const double *ind10,
                    double *e);

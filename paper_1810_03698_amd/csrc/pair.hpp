@@ -10,21 +10,29 @@
 
 namespace pbmp {
 
-// FP32 floor on r^2 (r >= 1e-4 A): pairs that close only occur between a
-// panel and itself or a near neighbour, whose coarse value is removed again
-// by the correction; it keeps coincident FP32 points finite.
+// FP32 cut-off on r^2 (r < 1e-4 A): such a pair adds nothing.  Pairs that
+// close only occur between a panel and itself (the one-node rule puts the
+// node on the centroid) or a near neighbour, and the near correction removes
+// exactly the value the product added, so skipping them is exact; it keeps
+// coincident FP32 points finite without 1/r-sized terms in FP32 sums.
 constexpr float kMinR2f = 1e-8f;
+// The FP64 products skip pairs closer than 1e-10 A: only a one-node rule's
+// node on its own panel's centroid comes that close (the node and the
+// centroid are computed with different roundings, so they need not
+// coincide exactly), since a node is at least a sixth of an altitude from
+// every other panel's centroid.
+constexpr double kMinR2d = 1e-20;
 
 // Reciprocal distance and screened reciprocal distance of one far-field
 // node for the difference R = p - y = (dx,dy,dz): ri = 1/r, er = e^{-k r}/r.
-// nk = -k log2(e).  FLOOR keeps r >= 1e-4 A.
+// nk = -k log2(e).  FLOOR: ri = er = 0 below the cut-off.
 template <bool FLOOR = true>
 __device__ __forceinline__ void node_core(float dx, float dy, float dz, float nk,
                                           float &ri, float &er) {
 #pragma clang fp contract(off)
-  float rr = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-  if (FLOOR) rr = fmaxf(rr, kMinR2f);
+  const float rr = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
   ri = __builtin_amdgcn_rsqf(rr);
+  if (FLOOR) ri = rr < kMinR2f ? 0.0f : ri;
   const float ek = __builtin_amdgcn_exp2f(nk * (rr * ri));
   er = ek * ri;
 }
@@ -49,10 +57,13 @@ __device__ __forceinline__ void node_terms(double dx, double dy, double dz,
                                            double &vy, double &kl, double &ky) {
 #pragma clang fp contract(off)
   const double rr = dx * dx + dy * dy + dz * dz;
+  // a node on the target (the one-node rule on a panel's own centroid)
+  // adds nothing, here and in the correction that removes it again
+  const bool on = rr < kMinR2d;
   const double rad = sqrt(rr);
-  const double ri = 1.0 / rad;
+  const double ri = on ? 0.0 : 1.0 / rad;
   const double ek = exp(-kappa * rad);
-  const double ri3 = ri / rr;
+  const double ri3 = on ? 0.0 : ri / rr;
   vl = vl + ri;
   vy = vy + ek * ri;
   kl = kl + ri3;

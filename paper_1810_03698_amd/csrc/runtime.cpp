@@ -326,10 +326,12 @@ void Runtime::set_mesh(int64_t nv, const double *verts, int64_t nt,
   for (int j = 0; j < N; ++j)
     PBMP_REQUIRE(h_geo_[6 * (size_t)N + j] > 1e-12, PBMP_EMESH,
                  "panel with area <= 1e-12 A^2");
-  // Far nodes are interior: a node lies at least (smallest altitude)/6 from
-  // its panel's boundary, hence from every other panel's centroid.  When
-  // that exceeds 1e-4 A plus the FP32 rounding of the coordinates, no FP32
-  // pair distance can fall below the floor and the product may skip it.
+  // The three far nodes are interior: a node lies at least (smallest
+  // altitude)/6 from its panel's boundary, hence from every other panel's
+  // centroid, and a third of a median from its own.  When that exceeds 1e-4 A
+  // plus the FP32 rounding of the coordinates, no FP32 pair distance can
+  // fall below the cut-off and the product may skip the test.  The one-node
+  // rule puts the node on its own centroid, so it always needs the test.
   {
     double min_alt = 1e300, max_abs = 0.0;
     for (int j = 0; j < N; ++j) {
@@ -346,7 +348,7 @@ void Runtime::set_mesh(int64_t nv, const double *verts, int64_t nt,
       }
       min_alt = std::min(min_alt, 2.0 * h_geo_[6 * (size_t)N + j] / std::sqrt(len2));
     }
-    floor_r2_ = !(min_alt / 6.0 > 1e-4 + 1e-6 * max_abs);
+    floor_r2_ = o.gauss_far == 1 || !(min_alt / 6.0 > 1e-4 + 1e-6 * max_abs);
   }
   build_near_lists();
   // --- tree
@@ -520,7 +522,7 @@ void Runtime::set_sites(int64_t m, const double *xyz, const double *q,
   p_.alloc(3 * (size_t)M);
   f_.alloc(N_);
   dmu2_.alloc(1);
-  e_.alloc(4);
+  e_.alloc(10);
   ro_chunks_ = std::max(1, std::min(64, (2048 + M - 1) / M));
   ro_chunks_ = std::min(ro_chunks_, std::max(1, N_ / 256));
   rpart_.alloc((size_t)ro_chunks_ * M * 10);
@@ -889,7 +891,8 @@ int Runtime::solve(pbmp_result *r) {
   launch_perm_potential(s_, M_, sxyz_.p, sq_.p, sd_.p, sQ_.p, o.eps_in, vac_perm_.p);
   launch_induced(s_, true, M_, sxyz_.p, mu_v_.p, salpha_.p, o.thole_a, o.eps_in, vac_ind_.p);
   launch_energy(s_, M_, sq_.p, sd_.p, sQ_.p, vac_perm_.p, vac_ind_.p, e_.p + 2);
-  double e[4];
+  launch_total_dipole(s_, M_, sxyz_.p, sq_.p, sd_.p, mu_v_.p, mu_d_.p, e_.p + 4);
+  double e[10];
   PBMP_HIP(hipMemcpyAsync(e, e_.p, sizeof(e), hipMemcpyDeviceToHost, s_));
   sync();
   const double C = coulomb_kcal();
@@ -897,6 +900,10 @@ int Runtime::solve(pbmp_result *r) {
   r->dG_pol_kcal = C * e[1];
   r->dG_kcal = C * (e[0] + e[1]);
   r->G_vac_kcal = C * (e[2] + e[3]);
+  for (int c = 0; c < 3; ++c) {
+    r->dipole_vac_debye[c] = debye_per_e_ang() * e[4 + c];
+    r->dipole_diss_debye[c] = debye_per_e_ang() * e[7 + c];
+  }
   warm_ok_ = true;
   r->scf_iters = std::abs(it_d);
   r->scf_iters_vac = std::abs(it_v);

@@ -94,7 +94,7 @@ class Runtime {
   Dbuf<int> trow_, tcol_;  // transposed near structure (entry ids)
   Dbuf<int> tent_;
   bool tree_active_ = false;
-  bool floor_r2_ = true;  // FP32 distance floor needed (tiny panels present)
+  bool floor_r2_ = true;  // FP32 distance cut-off needed (one-node rule, tiny panels)
   std::unique_ptr<Tree> tree_;
 
   // ---- sites ----

@@ -25,7 +25,10 @@ constexpr int kM2PChunkBoxes = PBMP_M2P_CHUNK;
 constexpr int kP2PTaskWork = PBMP_P2P_WORK;
 constexpr int kM2PTaskWork = PBMP_M2P_WORK;
 // panels per moment task
-constexpr int kMomChunkPanels = 2048;
+#ifndef PBMP_MOM_CHUNK
+#define PBMP_MOM_CHUNK 2048
+#endif
+constexpr int kMomChunkPanels = PBMP_MOM_CHUNK;
 // target panels per M2P^T task (adjoint product)
 constexpr int kM2PTChunkTargets = 512;
 

@@ -46,7 +46,9 @@ class Result(ctypes.Structure):
                 ("gmres_iters_total", ctypes.c_int), ("matvecs", ctypes.c_int),
                 ("final_relres", ctypes.c_double), ("t_setup_ms", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("t_matvec_ms", ctypes.c_double),
-                ("G_vac_kcal", ctypes.c_double)]
+                ("G_vac_kcal", ctypes.c_double),
+                ("dipole_vac_debye", ctypes.c_double * 3),
+                ("dipole_diss_debye", ctypes.c_double * 3)]
 
 
 class KernelStats(ctypes.Structure):
@@ -268,7 +270,9 @@ class Solver:
                    scf_iters_vac=r.scf_iters_vac, gmres_iters=r.gmres_iters_total,
                    matvecs=r.matvecs, relres=r.final_relres,
                    t_setup_ms=r.t_setup_ms, t_solve_ms=r.t_solve_ms,
-                   t_matvec_ms=r.t_matvec_ms)
+                   t_matvec_ms=r.t_matvec_ms,
+                   dipole_vac=np.array(r.dipole_vac_debye[:]),
+                   dipole_diss=np.array(r.dipole_diss_debye[:]))
         out.update(keep)
         return out
 

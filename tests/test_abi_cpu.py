@@ -44,7 +44,7 @@ def _struct_fields(name):
             continue
         parts = decl.replace("*", " ").split()
         for f in " ".join(parts[1:]).split(","):
-            fields.append(f.strip())
+            fields.append(re.sub(r"\[\d+\]$", "", f.strip()))
     return fields
 
 

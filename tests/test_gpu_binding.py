@@ -40,7 +40,10 @@ def _triad():
     h = 1.1
 
     def part(pos, rad, m):
+        # 1e-3 A jitter: no centroid distance sits exactly on the near-field
+        # threshold (the mesher's grid-aligned panels are congruent)
         v, t = molecule_mesh(pos, rad, h)
+        v = v + np.random.default_rng([12, len(t)]).normal(scale=1e-3, size=v.shape)
         q, d, Q9, al = m
         return dict(verts=v, tris=t, xyz=pos, q=q, d=d, Q9=Q9, alpha=al, radii=rad)
 

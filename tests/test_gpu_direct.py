@@ -26,11 +26,14 @@ def _solver(w, **kw):
 
 def _ragged():
     """A small irregular molecule: panel and site counts are not multiples
-    of any tile size."""
+    of any tile size.  The vertices are jittered by 1e-3 A: the mesher's
+    grid-aligned panels are otherwise congruent, with centroid distances
+    landing exactly on the near-field threshold."""
     rng = np.random.default_rng(7)
     pos, rad = saw_molecule(rng, 23, rg_target=4.0)
     q, d, Q9, alpha = random_multipoles(rng, 23)
     verts, tris = molecule_mesh(pos, rad, 1.0)
+    verts = verts + np.random.default_rng(70).normal(scale=1e-3, size=verts.shape)
     p = dict(eps_in=1.0, eps_out=80.0, kappa=0.125)
     return dict(verts=verts, tris=tris, xyz=pos, q=q, d=d, Q9=Q9,
                 alpha=alpha, params=p)
@@ -125,6 +128,9 @@ def test_solve_fp64_matches_oracle(cfg0):
     assert got["scf_iters"] == ref["scf_iters"]
     assert np.abs(got["mu_diss"] - ref["mu_diss"]).max() < 1e-10 * np.abs(ref["mu_diss"]).max()
     assert np.abs(got["mu_vac"] - ref["mu_vac"]).max() < 1e-12 * np.abs(ref["mu_vac"]).max()
+    for k in ("dipole_vac", "dipole_diss"):
+        print(k, got[k], ref[k])
+        assert np.abs(got[k] - ref[k]).max() < 1e-10 * np.abs(ref[k]).max()
     x = 4 * np.pi * ref["x"]
     N = len(w["tris"])
     assert np.abs(got["phi"] - x[:N]).max() < 1e-9 * np.abs(x[:N]).max()
@@ -146,16 +152,25 @@ def test_solve_mixed_within_1e4(cfg0, ragged):
 def test_mixed_refinement_reaches_fp64(cfg0, ragged):
     """A tolerance below the FP32 far field's residual floor is reached by
     recomputing restart residuals with the FP64 product (iterative
-    refinement): the mixed solve then matches the FP64 solve far beyond the
-    1e-4 of mixed precision."""
+    refinement): the mixed solve's final surface solution has an FP64
+    residual far below the FP32 product's floor (~1e-7), checked with the
+    FP64 operator against the right-hand side of the returned dipoles
+    (one relaxation step, under 1e-10 D, after the last solve's).  The
+    energy still carries the FP32 far field of the site readout (1e-7)."""
     for w in (cfg0, ragged):
         kw = dict(gmres_tol=1e-11, scf_tol_debye=1e-10, scf_maxit=500)
         got = _solver(w, precision="mixed", **kw).solve()
-        ref = _solver(w, precision="fp64", **kw).solve()
+        s64 = _solver(w, precision="fp64", **kw)
+        x = np.concatenate([got["phi"], got["dphidn"]]) / (4 * np.pi)
+        f = s64.rhs(w["d"] + got["mu_diss"])
+        b = np.concatenate([f, np.zeros_like(f)])
+        res = np.linalg.norm(b - s64.matvec(x)) / np.linalg.norm(b)
+        ref = s64.solve()
         rel = abs(got["dG"] - ref["dG"]) / abs(ref["dG"])
-        print("refined mixed dG", got["dG"], ref["dG"], rel, got["relres"])
+        print("refined mixed dG", got["dG"], ref["dG"], rel, got["relres"], "fp64 residual", res)
         assert got["status"] == 0 and got["relres"] <= 1e-11
-        assert rel < 1e-9
+        assert res < 1e-10
+        assert rel < 1e-7
 
 
 # ------------------------------------------------------------ error paths

@@ -467,6 +467,33 @@ def test_vacuum_energy_closed_forms():
     assert abs(G - (-C * 1.3 * 0.8 ** 2 / (2 * 3.0 ** 4))) < 1e-10 * abs(G)
 
 
+def test_total_dipole_units_and_origin():
+    """Total dipole (Table "dipole", Debye): a unit charge pair 1 A apart is
+    the textbook 4.803 D; a neutral set does not depend on the origin; a
+    charged one moves by Q times the origin shift; permanent and induced
+    dipoles add as vectors."""
+    xyz = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    q = np.array([-1.0, 1.0])
+    z = np.zeros((2, 3))
+    p = solver.total_dipole(xyz, q, z, z)
+    assert abs(p[2] - 4.80320) < 1e-5 and abs(p[0]) + abs(p[1]) == 0.0
+    rng = np.random.default_rng(7)
+    xyz = rng.normal(size=(9, 3))
+    q = rng.normal(size=9)
+    d, mu = rng.normal(size=(9, 3)), rng.normal(size=(9, 3))
+    qn = q - q.mean()
+    shift = np.array([3.0, -1.0, 2.0])
+    a = solver.total_dipole(xyz, qn, d, mu, origin=np.zeros(3))
+    b = solver.total_dipole(xyz, qn, d, mu, origin=shift)
+    assert np.abs(a - b).max() < 1e-12 * np.abs(a).max()
+    a = solver.total_dipole(xyz, q, d, mu, origin=np.zeros(3))
+    b = solver.total_dipole(xyz, q, d, mu, origin=shift)
+    assert np.abs((a - b) / mp.DEBYE_PER_EA - q.sum() * shift).max() < 1e-12
+    pd = solver.total_dipole(xyz, np.zeros(9), d, z)
+    pm = solver.total_dipole(xyz, np.zeros(9), z, mu)
+    assert np.abs(pd + pm - solver.total_dipole(xyz, np.zeros(9), d, mu)).max() < 1e-12
+
+
 def test_vacuum_binding_vanishes_at_separation():
     """G_AB - G_A - G_B tends to the monopole interaction of the two parts
     as they move apart."""
