@@ -48,12 +48,61 @@ __global__ void k_gemv_sub(int n, int nv, const double *__restrict__ V, size_t l
   w[i] -= s;
 }
 
+// The Arnoldi step's reductions without separate final passes: every
+// block of the consuming kernel adds the k_mdot_partial block sums itself
+// (nv * nblk values, in the order of k_mdot_final, so all blocks hold the
+// same totals) and block 0 also stores them for the host.
+constexpr int kMaxNV = 256;
+
+__device__ inline void sum_partials(int nv, int nblk, const double *__restrict__ partial,
+                                    double *h, double *__restrict__ hout) {
+  for (int k = threadIdx.x; k < nv; k += blockDim.x) {
+    const double *pk = partial + (size_t)k * nblk;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += pk[b];
+    h[k] = s;
+    if (blockIdx.x == 0) hout[k] = s;
+  }
+  __syncthreads();
+}
+
+// w -= V h with h summed from the partials (stored to hout by block 0)
+__global__ __launch_bounds__(kB) void k_gemv_sub_p(int n, int nv, const double *__restrict__ V,
+                                                   size_t ld, int nblk,
+                                                   const double *__restrict__ partial,
+                                                   double *__restrict__ hout,
+                                                   double *__restrict__ w) {
+  __shared__ double h[kMaxNV];
+  sum_partials(nv, nblk, partial, h, hout);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < nv; ++k) s += V[(size_t)k * ld + i] * h[k];
+  w[i] -= s;
+}
+
+// v = w / |w| with |w|^2 summed from the partials (stored to hout by block 0)
+__global__ __launch_bounds__(kB) void k_scale_inv_sqrt_p(int n, int nblk,
+                                                         const double *__restrict__ partial,
+                                                         double *__restrict__ hout,
+                                                         const double *__restrict__ w,
+                                                         double *__restrict__ v) {
+  __shared__ double h[1];
+  sum_partials(1, nblk, partial, h, hout);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double q = h[0];
+  v[i] = q > 0.0 ? w[i] / sqrt(q) : 0.0;
+}
+
+// v = w / sqrt(nrm2); a zero vector (Arnoldi breakdown) stays zero
 __global__ void k_scale_inv_sqrt(int n, const double *__restrict__ w,
                                  const double *__restrict__ nrm2,
                                  double *__restrict__ v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  v[i] = w[i] / sqrt(*nrm2);
+  const double q = *nrm2;
+  v[i] = q > 0.0 ? w[i] / sqrt(q) : 0.0;
 }
 
 __global__ void k_axpy(int n, double a, const double *__restrict__ x,
@@ -135,6 +184,29 @@ void launch_mdot(hipStream_t s, int n, int nv, const double *V, size_t ld,
                      w, per, partial);
   hipLaunchKernelGGL(k_mdot_final, dim3((nv + 63) / 64), dim3(64), 0, s, nv,
                      nblk, partial, h);
+  PBMP_HIP(hipGetLastError());
+}
+
+int launch_mdot_partial(hipStream_t s, int n, int nv, const double *V, size_t ld,
+                        const double *w, double *partial) {
+  const int per = 4096;
+  const int nblk = (n + per - 1) / per;
+  hipLaunchKernelGGL(k_mdot_partial, dim3(nblk, nv), dim3(kB), 0, s, n, V, ld, w, per,
+                     partial);
+  PBMP_HIP(hipGetLastError());
+  return nblk;
+}
+
+void launch_gemv_sub_p(hipStream_t s, int n, int nv, const double *V, size_t ld, int nblk,
+                       const double *partial, double *hout, double *w) {
+  if (nv > kMaxNV) throw Error(PBMP_EARG, "too many Krylov vectors");
+  hipLaunchKernelGGL(k_gemv_sub_p, g1(n), dim3(kB), 0, s, n, nv, V, ld, nblk, partial, hout, w);
+  PBMP_HIP(hipGetLastError());
+}
+
+void launch_scale_inv_sqrt_p(hipStream_t s, int n, int nblk, const double *partial,
+                             double *hout, const double *w, double *v) {
+  hipLaunchKernelGGL(k_scale_inv_sqrt_p, g1(n), dim3(kB), 0, s, n, nblk, partial, hout, w, v);
   PBMP_HIP(hipGetLastError());
 }
 

@@ -18,6 +18,8 @@
 // launch; no upward shifts).
 #include <cmath>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "pair.hpp"
 #include "runtime.hpp"
@@ -75,20 +77,23 @@ __device__ inline int xcd_task(int ntasks) {
 }
 
 // ---------------------------------------------------------------- P2M
-// Moments of every box that some target leaf accepts, straight from its
-// nodes (every box is a contiguous panel range): one 256-lane block per
-// task, a task being a box's panels [s0, s1) or a slice of at most
-// kMomChunkPanels of them.  Every lane takes nodes, builds all monomials h^k
-// incrementally (each from its parent multi-index) and accumulates both
-// moment sets in registers; a wave reduction (shuffles) and an LDS reduction
-// across the four waves give the task's partial moments, and k_mom_reduce
-// adds a box's slices in a fixed order.  Computing every level from the
-// nodes replaces the upward shifts (M2M) with one launch and no
-// accumulated shift rounding.
+// Moments of every leaf straight from its nodes (every box is a contiguous
+// panel range): one block (one wave by default) per task, a task being a
+// leaf's panels [s0, s1) or a slice of at most mom_chunk_panels(P) of them.
+// Every lane takes nodes, builds all monomials h^k incrementally (each from
+// its parent multi-index) and accumulates both moment sets in registers; a
+// wave reduction (shuffles), and an LDS reduction across waves when a block
+// has several, give the task's partial moments, and k_mom_reduce adds a
+// leaf's slices in a fixed order.  The accepted boxes above the leaves then
+// take their moments from the leaves' by exact shifts (k_shift_tasks): two
+// short launches instead of walking every box's nodes, whose long tasks and
+// few waves left the direct form latency-bound.
 #ifndef PBMP_P2M_THREADS
-#define PBMP_P2M_THREADS 256
+#define PBMP_P2M_THREADS 64
 #endif
 constexpr int kP2MThreads = PBMP_P2M_THREADS;
+constexpr int kP2MTile = 64;  // panels per LDS tile (64 and 192 nodes: multiples of 64)
+static_assert(kP2MThreads % 64 == 0 && kP2MTile % kP2MThreads == 0, "P2M tiling");
 
 template <int P>
 __global__ __launch_bounds__(kP2MThreads) void k_p2m_tasks(int nf, const int *__restrict__ tasks,
@@ -105,28 +110,62 @@ __global__ __launch_bounds__(kP2MThreads) void k_p2m_tasks(int nf, const int *__
   double m[NC], mk[NC];
 #pragma unroll
   for (int k = 0; k < NC; ++k) m[k] = mk[k] = 0.0;
-  const int nnode = (s1 - s0) * nf;
-  for (int g = threadIdx.x; g < nnode; g += kP2MThreads) {
-    const int j = s0 + g / nf, q = g % nf;
-    const double *r = src + 16 * (size_t)j;
-    const double h[3] = {r[3 * q] - c[0], r[3 * q + 1] - c[1], r[3 * q + 2] - c[2]};
-    const double n[3] = {r[9], r[10], r[11]};
-    const double sv = r[13], sk = r[14];
-    double mono[NC];
-    mono[0] = 1.0;
+  // the slice's panel records pass through LDS in tiles of kP2MTile
+  // (coalesced loads, all issued together); records padded to 17 doubles
+  // against bank conflicts.  A tile holds a multiple of 64 nodes, so every
+  // lane takes the same nodes in the same order as without staging.
+  __shared__ double sh[kP2MTile * 17];
+  for (int jt = s0; jt < s1; jt += kP2MTile) {
+    const int nj = min(kP2MTile, s1 - jt);
+    __syncthreads();
+    {
+      // 16-byte loads, two in flight per round (a plain copy loop waits for
+      // each load before its store)
+      constexpr int U = kP2MTile * 8 / kP2MThreads, Bk = 2;
+      typedef double d2 __attribute__((ext_vector_type(2)));
+      const d2 *s2 = reinterpret_cast<const d2 *>(src + (size_t)jt * 16);
 #pragma unroll
-    for (int k = 1; k < NC; ++k) {
-      const int d = mi.e[k][0] ? 0 : (mi.e[k][1] ? 1 : 2);
-      mono[k] = mono[mi.m1[k][d]] * h[d];
+      for (int u0 = 0; u0 < U; u0 += Bk) {
+        d2 buf[Bk];
+#pragma unroll
+        for (int u = 0; u < Bk; ++u) {
+          const int e = threadIdx.x + (u0 + u) * kP2MThreads;
+          if (e < nj * 8) buf[u] = s2[e];
+        }
+#pragma unroll
+        for (int u = 0; u < Bk; ++u) {
+          const int e = threadIdx.x + (u0 + u) * kP2MThreads;
+          if (e < nj * 8) {
+            double *d = sh + 17 * (e >> 3) + 2 * (e & 7);
+            d[0] = buf[u].x;
+            d[1] = buf[u].y;
+          }
+        }
+      }
     }
+    __syncthreads();
+    for (int g = threadIdx.x; g < nj * nf; g += kP2MThreads) {
+      const int q = g % nf;
+      const double *r = sh + 17 * (g / nf);
+      const double h[3] = {r[3 * q] - c[0], r[3 * q + 1] - c[1], r[3 * q + 2] - c[2]};
+      const double n[3] = {r[9], r[10], r[11]};
+      const double sv = r[13], sk = r[14];
+      double mono[NC];
+      mono[0] = 1.0;
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      m[k] += sv * mono[k];
-      double dk = 0.0;
+      for (int k = 1; k < NC; ++k) {
+        const int d = mi.e[k][0] ? 0 : (mi.e[k][1] ? 1 : 2);
+        mono[k] = mono[mi.m1[k][d]] * h[d];
+      }
 #pragma unroll
-      for (int d = 0; d < 3; ++d)
-        if (mi.m1[k][d] >= 0) dk += mi.e[k][d] * n[d] * mono[mi.m1[k][d]];
-      mk[k] += sk * dk;
+      for (int k = 0; k < NC; ++k) {
+        m[k] += sv * mono[k];
+        double dk = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          if (mi.m1[k][d] >= 0) dk += mi.e[k][d] * n[d] * mono[mi.m1[k][d]];
+        mk[k] += sk * dk;
+      }
     }
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -151,23 +190,111 @@ __global__ __launch_bounds__(kP2MThreads) void k_p2m_tasks(int nf, const int *__
 }
 
 // mom[B] = sum of the partial moments of B's slices, in slice order
+// (mom32: the FP32 copy the mixed-precision M2P reads, or null)
 __global__ void k_mom_reduce(int nbox, int ncoef2, const int *__restrict__ first,
                              const int *__restrict__ count, const double *__restrict__ part,
-                             double *__restrict__ mom) {
+                             double *__restrict__ mom, float *__restrict__ mom32) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nbox * ncoef2) return;
   const int B = e / ncoef2, k = e % ncoef2;
   const int t0 = first[B], nt = count[B];
-  if (nt == 0) return;  // never accepted: no moments needed
+  if (nt == 0) return;  // not this pass's box (or not needed)
   double v = 0.0;
   for (int t = t0; t < t0 + nt; ++t) v += part[(size_t)t * ncoef2 + k];
   mom[e] = v;
+  if (mom32) mom32[e] = (float)v;
 }
 
-__global__ void k_cast(size_t n, const double *__restrict__ a, float *__restrict__ b) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = (float)a[i];
+// Moments of the accepted boxes with children from the leaf moments: with
+// d = c_L - c_B, (h + d)^k = sum_{j <= k} C(k, j) d^(k-j) h^j, and the
+// double-layer moments (n . grad_h) h^k shift with the same coefficients,
+// so m_k(B) = sum over the leaves L under B of sum_{j <= k} C(k, j)
+// d^(k-j) m_j(L), for both moment sets.  One wave per task (a run of at
+// most kShiftLeaves of a box's leaves): the moments of all the run's
+// leaves and the monomials of their d are staged in LDS with every load
+// issued together, then each lane owns coefficients k and walks its terms
+// (j, k - j, C(k, j)) from a table, leaf by leaf in order.
+constexpr int kShiftThreads = 64;
+
+template <int P>
+__global__ __launch_bounds__(kShiftThreads) void k_shift_tasks(
+    const int *__restrict__ tasks, const int *__restrict__ leaves,
+    const double *__restrict__ center, const int *__restrict__ monos,
+    const int *__restrict__ toff, const int *__restrict__ tjq,
+    const double *__restrict__ tc, const double *__restrict__ mom,
+    double *__restrict__ part) {
+  constexpr int NC = (P + 1) * (P + 2) * (P + 3) / 6;
+  constexpr int R = (NC + kShiftThreads - 1) / kShiftThreads;
+  __shared__ double sm[kShiftLeaves * 2 * NC], sd[kShiftLeaves * NC];
+  __shared__ int sL[kShiftLeaves];
+  const int B = tasks[3 * blockIdx.x];
+  const int la = tasks[3 * blockIdx.x + 1];
+  const int nl = tasks[3 * blockIdx.x + 2] - la;
+  const double cB[3] = {center[3 * B], center[3 * B + 1], center[3 * B + 2]};
+  __shared__ double sdl[kShiftLeaves * 3];
+  if (threadIdx.x < nl) {
+    const int L = leaves[la + threadIdx.x];
+    sL[threadIdx.x] = L;
+    for (int c = 0; c < 3; ++c) sdl[3 * threadIdx.x + c] = center[3 * L + c] - cB[c];
+  }
+  __syncthreads();
+  // moments with eight loads in flight per lane
+  for (int e0 = threadIdx.x; e0 < nl * 2 * NC; e0 += 8 * kShiftThreads) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * kShiftThreads;
+      if (e < nl * 2 * NC) v[u] = mom[(size_t)sL[e / (2 * NC)] * 2 * NC + e % (2 * NC)];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * kShiftThreads;
+      if (e < nl * 2 * NC) sm[e] = v[u];
+    }
+  }
+  for (int e = threadIdx.x; e < nl * NC; e += kShiftThreads) {
+    const int l = e / NC, k = e % NC;
+    double v = 1.0;
+    for (int c = 0; c < 3; ++c)
+      for (int u = 0; u < monos[3 * k + c]; ++u) v *= sdl[3 * l + c];
+    sd[e] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int k = threadIdx.x + r * kShiftThreads;
+    if (k >= NC) continue;
+    const int t0 = toff[k], t1 = toff[k + 1];
+    // terms outer (one table read each), leaves inner; per-leaf sums in
+    // registers are added in leaf order at the end
+    double v[kShiftLeaves], w[kShiftLeaves];
+#pragma unroll
+    for (int l = 0; l < kShiftLeaves; ++l) v[l] = w[l] = 0.0;
+    for (int t = t0; t < t1; ++t) {
+      const int j = tjq[2 * t], q = tjq[2 * t + 1];
+      const double ct = tc[t];
+#pragma unroll
+      for (int l = 0; l < kShiftLeaves; ++l) {
+        if (l < nl) {
+          const double c = ct * sd[l * NC + q];
+          v[l] += c * sm[l * 2 * NC + j];
+          w[l] += c * sm[l * 2 * NC + NC + j];
+        }
+      }
+    }
+    double aV = 0.0, aK = 0.0;
+#pragma unroll
+    for (int l = 0; l < kShiftLeaves; ++l) {
+      if (l < nl) {
+        aV += v[l];
+        aK += w[l];
+      }
+    }
+    part[(size_t)blockIdx.x * 2 * NC + k] = aV;
+    part[(size_t)blockIdx.x * 2 * NC + NC + k] = aK;
+  }
 }
+
 
 // ------------------------------------------------------------ P2P tasks
 // One 64-lane block per task: targets [t0, t1) of a leaf, sources = the
@@ -216,6 +343,37 @@ __device__ inline LaneSplit lane_split(int nt) {
   return best;
 }
 
+// Copies nj (<= MAXREC) records of 16 T from global memory to LDS in
+// 16-byte accesses, every load of the lane issued before the first store
+// (a plain copy loop waits for each load before its store).
+template <class T, int MAXREC>
+__device__ __forceinline__ void stage_records(const T *__restrict__ src, T *sh, int nj,
+                                              int lane) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  using V = typename std::conditional<sizeof(T) == 4, f4, d2>::type;
+  constexpr int PER = 16 * (int)sizeof(T) / 16;  // 16-byte units per record
+  constexpr int U = (MAXREC * PER + 63) / 64;
+  const V *s = reinterpret_cast<const V *>(src);
+  V *d = reinterpret_cast<V *>(sh);
+  constexpr int B = 2;  // loads in flight per round (registers of the caller stay free)
+  const int n = nj * PER;
+#pragma unroll
+  for (int u0 = 0; u0 < U; u0 += B) {
+    V buf[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int e = lane + 64 * (u0 + u);
+      if (u0 + u < U && e < n) buf[u] = s[e];
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int e = lane + 64 * (u0 + u);
+      if (u0 + u < U && e < n) d[e] = buf[u];
+    }
+  }
+}
+
 template <class T, int NF, int TPT, bool FLOOR>
 __device__ void p2p_task_body(const T *__restrict__ src, const T *__restrict__ tgt,
                               int N, int t0, int t1, const int *__restrict__ ranges,
@@ -244,7 +402,7 @@ __device__ void p2p_task_body(const T *__restrict__ src, const T *__restrict__ t
       for (int jt = s0; jt < s1; jt += kTileT) {
         const int nj = min(kTileT, s1 - jt);
         __syncthreads();
-        for (int e = lane; e < nj * 16; e += 64) sh[e] = src[(size_t)jt * 16 + e];
+        stage_records<T, kTileT>(src + (size_t)jt * 16, sh, nj, lane);
         __syncthreads();
         T a[TPT][4];
 #pragma unroll
@@ -378,11 +536,24 @@ __global__ __launch_bounds__(64) void k_m2p_tasks(int ntask, const int *__restri
   const int slot = slots[task];
   const int nb = le - lb;
   const int nt = t1 - t0;
-  for (int e = threadIdx.x; e < nb * 2 * NC; e += 64) {
-    const int b = e / (2 * NC), c = e % (2 * NC);
-    smom[e] = mom[(size_t)boxes[lb + b] * 2 * NC + c];
+  // box ids first, then the moments with eight loads in flight per lane
+  __shared__ int sbox[kM2PChunkBoxes];
+  if (threadIdx.x < nb) sbox[threadIdx.x] = boxes[lb + threadIdx.x];
+  __syncthreads();
+  for (int e0 = threadIdx.x; e0 < nb * 2 * NC; e0 += 8 * 64) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + 64 * u;
+      if (e < nb * 2 * NC) v[u] = mom[(size_t)sbox[e / (2 * NC)] * 2 * NC + e % (2 * NC)];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + 64 * u;
+      if (e < nb * 2 * NC) smom[e] = v[u];
+    }
   }
-  for (int e = threadIdx.x; e < nb * 3; e += 64) scen[e] = (T)center[3 * boxes[lb + e / 3] + e % 3];
+  for (int e = threadIdx.x; e < nb * 3; e += 64) scen[e] = (T)center[3 * sbox[e / 3] + e % 3];
   // optionally lanes in G groups of L = 64 / G (PBMP_M2P_GROUPS): a group
   // takes every G-th box for all targets, G maximising the useful fraction
   // nt nb / (64 ceil(nt/L) ceil(nb/G)); off by default (measured slower)
@@ -470,9 +641,45 @@ __global__ void k_finish_slots(int N, const int *__restrict__ tslots,
   if (i >= N) return;
   double S[4] = {0.0, 0.0, 0.0, 0.0};
   const int ns = tslots[i];
-  for (int c = 0; c < ns; ++c)
+  // slots in order, four at a time: the loads of four slots are issued
+  // before the first add (the kernel is bound by their latency)
+  int c = 0;
+  for (; c + 4 <= ns; c += 4) {
+    double v[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[u][k] = part[((size_t)(c + u) * 4 + k) * N + i];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) S[k] += v[u][k];
+  }
+  for (; c < ns; ++c)
     for (int k = 0; k < 4; ++k) S[k] += part[((size_t)c * 4 + k) * N + i];
-  for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+  const int e0 = rowptr[i], e1 = rowptr[i + 1];
+  int e = e0;
+  for (; e + 4 <= e1; e += 4) {
+    int jj[4];
+    double vv[4][4], ph[4], dp[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) jj[u] = col[e + u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ph[u] = x[jj[u]];
+      dp[u] = x[N + jj[u]];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) vv[u][k] = val[4 * (size_t)(e + u) + k];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      S[0] += vv[u][0] * dp[u];
+      S[1] += vv[u][1] * ph[u];
+      S[2] += vv[u][2] * dp[u];
+      S[3] += vv[u][3] * ph[u];
+    }
+  }
+  for (; e < e1; ++e) {
     const int j = col[e];
     const double ph = x[j], dp = x[N + j];
     S[0] += val[4 * (size_t)e] * dp;
@@ -508,24 +715,35 @@ void launch_m2p(Tree &t, hipStream_t s, const T *mom, const T *tgt, int N, T kap
   }
 }
 
-template <int P> void launch_moments_p(Tree &t, hipStream_t s, int nf, const double *src64) {
+template <int P>
+void launch_moments_p(Tree &t, hipStream_t s, int nf, const double *src64, float *mom32) {
   constexpr int NC = Multi<P>::n;
   if (t.n_mom_tasks == 0) return;
   hipLaunchKernelGGL(k_p2m_tasks<P>, dim3(t.n_mom_tasks), dim3(kP2MThreads), 0, s, nf,
                      t.d_mom_task.p, t.d_center.p, src64, t.d_mom_part.p);
   const int n = t.nbox * 2 * NC;
   hipLaunchKernelGGL(k_mom_reduce, dim3((n + 255) / 256), dim3(256), 0, s, t.nbox, 2 * NC,
-                     t.d_mom_first.p, t.d_mom_count.p, t.d_mom_part.p, t.d_mom64.p);
+                     t.d_mom_first.p, t.d_mom_count.p, t.d_mom_part.p, t.d_mom64.p, mom32);
+  if (t.n_shift_tasks > 0) {
+    hipLaunchKernelGGL(k_shift_tasks<P>, dim3(t.n_shift_tasks), dim3(kShiftThreads), 0, s,
+                       t.d_shift_task.p, t.d_leaves.p, t.d_center.p, t.d_monos.p,
+                       t.d_shift_toff.p, t.d_shift_tjq.p, t.d_shift_tc.p, t.d_mom64.p,
+                       t.d_shift_part.p);
+    hipLaunchKernelGGL(k_mom_reduce, dim3((n + 255) / 256), dim3(256), 0, s, t.nbox, 2 * NC,
+                       t.d_shift_first.p, t.d_shift_count.p, t.d_shift_part.p, t.d_mom64.p,
+                       mom32);
+  }
 }
 
-void launch_moments(Tree &t, hipStream_t s, int nf, const double *src64) {
+// moments in FP64, and their FP32 copy when mom32 is not null
+void launch_moments(Tree &t, hipStream_t s, int nf, const double *src64, float *mom32) {
   switch (t.prm.order) {
-    case 1: launch_moments_p<1>(t, s, nf, src64); break;
-    case 2: launch_moments_p<2>(t, s, nf, src64); break;
-    case 3: launch_moments_p<3>(t, s, nf, src64); break;
-    case 4: launch_moments_p<4>(t, s, nf, src64); break;
-    case 5: launch_moments_p<5>(t, s, nf, src64); break;
-    case 6: launch_moments_p<6>(t, s, nf, src64); break;
+    case 1: launch_moments_p<1>(t, s, nf, src64, mom32); break;
+    case 2: launch_moments_p<2>(t, s, nf, src64, mom32); break;
+    case 3: launch_moments_p<3>(t, s, nf, src64, mom32); break;
+    case 4: launch_moments_p<4>(t, s, nf, src64, mom32); break;
+    case 5: launch_moments_p<5>(t, s, nf, src64, mom32); break;
+    case 6: launch_moments_p<6>(t, s, nf, src64, mom32); break;
     default: throw Error(PBMP_EARG, "treecode order must be 1..6");
   }
 }
@@ -913,19 +1131,40 @@ void tree_upload_exponents(Tree &t, hipStream_t s) {
     for (int i = d; i >= 0; --i)
       for (int j = d - i; j >= 0; --j) ex.insert(ex.end(), {i, j, d - i - j});
   t.d_monos.upload(ex.data(), ex.size(), s);
+  // shift terms per coefficient k: (j, k - j, C(k, j)) for every j <= k
+  auto index = [](int i, int j, int l) {
+    const int d = i + j + l;
+    return d * (d + 1) * (d + 2) / 6 + (d - i) * (d - i + 1) / 2 + (d - i - j);
+  };
+  auto binom = [](int n, int r) {
+    double c = 1.0;
+    for (int u = 1; u <= r; ++u) c = c * (n - r + u) / u;
+    return c;
+  };
+  const int nc = (int)ex.size() / 3;
+  std::vector<int> off(nc + 1, 0), jq;
+  std::vector<double> c;
+  for (int k = 0; k < nc; ++k) {
+    const int kx = ex[3 * k], ky = ex[3 * k + 1], kz = ex[3 * k + 2];
+    for (int jx = 0; jx <= kx; ++jx)
+      for (int jy = 0; jy <= ky; ++jy)
+        for (int jz = 0; jz <= kz; ++jz) {
+          jq.push_back(index(jx, jy, jz));
+          jq.push_back(index(kx - jx, ky - jy, kz - jz));
+          c.push_back(binom(kx, jx) * binom(ky, jy) * binom(kz, jz));
+        }
+    off[k + 1] = (int)c.size();
+  }
+  t.d_shift_toff.upload(off.data(), off.size(), s);
+  t.d_shift_tjq.upload(jq.data(), jq.size(), s);
+  t.d_shift_tc.upload(c.data(), c.size(), s);
 }
 
 void tree_apply(Tree &t, hipStream_t s, bool fp64, int nf, int N, const double *geo,
                 const double *src64, const float *src32, const float *tgt32,
                 double kappa, double *part, KernelClock &clk, bool floor_r2) {
-  const int NC = t.ncoef;
   hipEvent_t e0 = clk.on ? clk.begin(s) : nullptr;
-  launch_moments(t, s, nf, src64);
-  if (!fp64) {
-    const size_t n = (size_t)t.nbox * 2 * NC;
-    hipLaunchKernelGGL(k_cast, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
-                       t.d_mom64.p, t.d_mom32.p);
-  }
+  launch_moments(t, s, nf, src64, fp64 ? nullptr : t.d_mom32.p);
   PBMP_HIP(hipGetLastError());
   if (clk.on) clk.end(s, e0, KernelClock::P2M, 0.0);
 

@@ -490,10 +490,54 @@ __global__ void k_need_moments(int n, const int *__restrict__ m2p_box, int *__re
   if (e < n) need[m2p_box[e]] = 1;  // every writer stores the same value
 }
 
-__global__ void k_mom_counts(int nbox, const int *__restrict__ need, Boxes b, int chunk,
-                             int *__restrict__ count) {
+// node tasks for the moments of every leaf (the inputs of every shift)
+__global__ void k_mom_counts(int nbox, Boxes b, int chunk, int *__restrict__ count) {
   const int B = blockIdx.x * blockDim.x + threadIdx.x;
-  if (B < nbox) count[B] = need[B] ? (b.end[B] - b.start[B] + chunk - 1) / chunk : 0;
+  if (B < nbox) count[B] = b.nchild[B] == 0 ? (b.end[B] - b.start[B] + chunk - 1) / chunk : 0;
+}
+
+__global__ void k_leaf_starts(int nleaf, const int *__restrict__ leaves, Boxes b,
+                              int *__restrict__ ls) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l < nleaf) ls[l] = b.start[leaves[l]];
+}
+
+__device__ inline int lower_bound_int(const int *a, int n, int v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// shift tasks of every accepted box with children: its leaves (a
+// contiguous run of the key-ordered leaves, those starting inside its
+// panel range) in runs of at most `chunk`
+__global__ void k_shift_counts(int nbox, const int *__restrict__ need, Boxes b,
+                               const int *__restrict__ ls, int nleaf, int chunk,
+                               int *__restrict__ range, int *__restrict__ count) {
+  const int B = blockIdx.x * blockDim.x + threadIdx.x;
+  if (B >= nbox) return;
+  const int l0 = lower_bound_int(ls, nleaf, b.start[B]);
+  const int l1 = lower_bound_int(ls, nleaf, b.end[B]);
+  range[2 * B] = l0;
+  range[2 * B + 1] = l1;
+  count[B] = (need[B] && b.nchild[B] > 0) ? (l1 - l0 + chunk - 1) / chunk : 0;
+}
+
+__global__ void k_shift_fill(int nbox, const int *__restrict__ first,
+                             const int *__restrict__ count, const int *__restrict__ range,
+                             int chunk, int *__restrict__ task) {
+  const int B = blockIdx.x * blockDim.x + threadIdx.x;
+  if (B >= nbox) return;
+  for (int k = 0; k < count[B]; ++k) {
+    int *tk = task + 3 * (first[B] + k);
+    tk[0] = B;
+    tk[1] = range[2 * B] + k * chunk;
+    tk[2] = min(range[2 * B + 1], range[2 * B] + (k + 1) * chunk);
+  }
 }
 
 __global__ void k_mom_fill(int nbox, const int *__restrict__ first,
@@ -708,13 +752,29 @@ void Tree::build_device(int N, int nf, const uint64_t *key, const double *geo,
                          n_m2p_entries, d_m2p_box.p, need.p);
     d_mom_count.alloc(nbox);
     d_mom_first.alloc(nbox);
-    hipLaunchKernelGGL(k_mom_counts, grid_for(nbox), dim3(256), 0, s, nbox, need.p, view(),
-                       kMomChunkPanels, d_mom_count.p);
+    hipLaunchKernelGGL(k_mom_counts, grid_for(nbox), dim3(256), 0, s, nbox, view(),
+                       mom_chunk_panels(prm.order), d_mom_count.p);
     n_mom_tasks = exclusive_scan_total(s, d_mom_count.p, d_mom_first.p, nbox, tmp);
     d_mom_task.alloc(3 * (size_t)std::max(1, n_mom_tasks));
     hipLaunchKernelGGL(k_mom_fill, grid_for(nbox), dim3(256), 0, s, nbox, d_mom_first.p,
-                       d_mom_count.p, view(), kMomChunkPanels, d_mom_task.p);
+                       d_mom_count.p, view(), mom_chunk_panels(prm.order), d_mom_task.p);
     d_mom_part.alloc((size_t)std::max(1, n_mom_tasks) * 2 * ncoef);
+    // shifts of the leaf moments to the accepted boxes above them
+    Dbuf<int> ls, range;
+    ls.alloc(std::max(1, nleaf));
+    range.alloc(2 * (size_t)nbox);
+    hipLaunchKernelGGL(k_leaf_starts, grid_for(nleaf), dim3(256), 0, s, nleaf, d_leaves.p,
+                       view(), ls.p);
+    d_shift_count.alloc(nbox);
+    d_shift_first.alloc(nbox);
+    hipLaunchKernelGGL(k_shift_counts, grid_for(nbox), dim3(256), 0, s, nbox, need.p, view(),
+                       ls.p, nleaf, kShiftLeaves, range.p, d_shift_count.p);
+    n_shift_tasks = exclusive_scan_total(s, d_shift_count.p, d_shift_first.p, nbox, tmp);
+    d_shift_task.alloc(3 * (size_t)std::max(1, n_shift_tasks));
+    hipLaunchKernelGGL(k_shift_fill, grid_for(nbox), dim3(256), 0, s, nbox, d_shift_first.p,
+                       d_shift_count.p, range.p, kShiftLeaves, d_shift_task.p);
+    d_shift_part.alloc((size_t)std::max(1, n_shift_tasks) * 2 * ncoef);
+    PBMP_HIP(hipStreamSynchronize(s));
     PBMP_HIP(hipGetLastError());
   }
   d_mom64.alloc((size_t)nbox * 2 * ncoef);

@@ -119,7 +119,18 @@ void launch_mdot(hipStream_t s, int n, int nv, const double *V, size_t ld,
 // w -= sum_k V[k*ld + i] h[k]
 void launch_gemv_sub(hipStream_t s, int n, int nv, const double *V, size_t ld,
                      const double *h, double *w);
-// v = w * (1/ *nrm) with nrm = sqrt(*nrm2)
+// Arnoldi-step forms without the final reduction launch: the block sums of
+// launch_mdot_partial (returns their count per vector) are added by every
+// block of the consumer in a fixed order; block 0 stores the totals to hout.
+// gemv_sub_p: w -= V h (nv <= 256); scale_inv_sqrt_p: v = w / |w| (zero
+// stays zero).
+int launch_mdot_partial(hipStream_t s, int n, int nv, const double *V, size_t ld,
+                        const double *w, double *partial);
+void launch_gemv_sub_p(hipStream_t s, int n, int nv, const double *V, size_t ld, int nblk,
+                       const double *partial, double *hout, double *w);
+void launch_scale_inv_sqrt_p(hipStream_t s, int n, int nblk, const double *partial,
+                             double *hout, const double *w, double *v);
+// v = w * (1/ *nrm) with nrm = sqrt(*nrm2); zero when *nrm2 is zero
 void launch_scale_inv_sqrt(hipStream_t s, int n, const double *w,
                            const double *nrm2, double *v);
 void launch_axpy(hipStream_t s, int n, double a, const double *x, double *y);

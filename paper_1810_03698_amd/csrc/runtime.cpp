@@ -246,6 +246,8 @@ Runtime::~Runtime() {
   } catch (...) {
   }
   if (s_) (void)hipStreamSynchronize(s_);
+  for (hipEvent_t e : kev_) (void)hipEventDestroy(e);
+  if (hpin_) (void)hipHostFree(hpin_);
   if (own_stream_ && s_) (void)hipStreamDestroy(s_);
 }
 
@@ -604,75 +606,114 @@ void Runtime::apply(const double *x, double *y, bool f64) {
 
 // ----------------------------------------------------------------- GMRES
 // Right-preconditioned restarted GMRES with classical Gram-Schmidt applied
-// twice, Givens rotations on the host, and the true residual recomputed at
-// every restart.
-int Runtime::gmres(const double *b, double *x, bool transpose, int *iters) {
-  const int N = N_, n = 2 * N, m = o.gmres_restart;
+// twice, the true residual recomputed at every restart.  The Arnoldi steps
+// run on the device; each step's Hessenberg column is copied to pinned host
+// memory and rotated there (Givens).  The host launches the next step
+// before it has read the current one's column whenever the residual
+// estimate cannot reach the tolerance within the current step, so the
+// device never waits for the host: with r the last known residual and rho
+// the smallest of the last three reduction ratios, the next step is
+// launched early when r rho exceeds the target.  A step launched early past
+// convergence only extends the Krylov basis; the update uses the converged
+// columns.
+void Runtime::krylov_reserve(int n) {
+  const int m = o.gmres_restart;
+  partial_.reserve((size_t)(m + 2) * ((n + 4095) / 4096 + 1));
+  hbuf_.reserve(3 * (size_t)(m + 2));
+  ybuf_.reserve((size_t)(m + 2));
+  const size_t need = (size_t)m * 3 * (m + 2);
+  if (hpin_n_ < need) {
+    if (hpin_) PBMP_HIP(hipHostFree(hpin_));
+    hpin_ = nullptr;
+    hpin_n_ = 0;
+    PBMP_HIP(hipHostMalloc((void **)&hpin_, need * sizeof(double), hipHostMallocDefault));
+    hpin_n_ = need;
+  }
+  while ((int)kev_.size() < m) {
+    hipEvent_t e;
+    PBMP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    kev_.push_back(e);
+  }
+}
+
+int Runtime::gmres_core(int n, const KOp &op, const KPrec &prec, const KUpdate &update,
+                        const double *b, double *x, double *V, double *w, double *z,
+                        double *ax, int *iters) {
+  const int m = o.gmres_restart;
   const size_t ld = n;
-  auto op = [&](const double *in, double *out, bool f64) {
-    if (transpose) apply_transpose(in, out, f64);
-    else apply(in, out, f64);
+  const size_t stride = 3 * (size_t)(m + 2);
+  krylov_reserve(n);
+  auto dot_host = [&](const double *a, const double *bb) {
+    launch_mdot(s_, n, 1, a, ld, bb, partial_.p, hbuf_.p);
+    double h;
+    PBMP_HIP(hipMemcpyAsync(&h, hbuf_.p, sizeof(double), hipMemcpyDeviceToHost, s_));
+    sync();
+    return h;
   };
+  const double bnorm = std::sqrt(dot_host(b, b));
+  *iters = 0;
+  if (bnorm == 0.0) {
+    launch_scale(s_, n, 0.0, x, x);
+    last_relres_ = 0.0;
+    return 0;
+  }
   // Mixed precision: restart residuals come from the FP32-far-field product
   // while they keep falling; once a cycle stalls (the residual floor of that
   // product), they are recomputed with the FP64 product, which turns the
   // restarts into iterative refinement with FP64 residuals.
   bool refine = false;
   double prev = 0.0;
-  auto dot_host = [&](const double *a, const double *bb) {
-    launch_mdot(s_, n, 1, a, ld, bb, partial_.p, hbuf_.p);
-    double h;
-    PBMP_HIP(hipMemcpyAsync(&h, hbuf_.p, sizeof(double), hipMemcpyDeviceToHost, s_));
-    sync();
-    return h;
-  };
-  const double bnorm = std::sqrt(dot_host(b, b));
-  *iters = 0;
-  if (bnorm == 0.0) {
-    PBMP_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s_));
-    last_relres_ = 0.0;
-    return 0;
-  }
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hh(3 * (m + 2)), y(m);
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  double ratio[3] = {0.1, 0.1, 0.1};
   int it = 0;
   while (true) {
-    op(x, ax_.p, refine);
-    launch_xmy(s_, n, b, ax_.p, w_.p);
-    double beta = std::sqrt(dot_host(w_.p, w_.p));
+    op(x, ax, refine);
+    launch_xmy(s_, n, b, ax, w);
+    double beta = std::sqrt(dot_host(w, w));
     if (!refine && !fp64() && it > 0 && beta / bnorm > 0.5 * prev && beta / bnorm > o.gmres_tol) {
       refine = true;
-      op(x, ax_.p, true);
-      launch_xmy(s_, n, b, ax_.p, w_.p);
-      beta = std::sqrt(dot_host(w_.p, w_.p));
+      op(x, ax, true);
+      launch_xmy(s_, n, b, ax, w);
+      beta = std::sqrt(dot_host(w, w));
     }
     last_relres_ = beta / bnorm;
     prev = last_relres_;
     if (last_relres_ <= o.gmres_tol) return 0;
     if (it >= o.gmres_maxit) return PBMP_WGMRES;
-    launch_scale(s_, n, 1.0 / beta, w_.p, V_.p);
+    launch_scale(s_, n, 1.0 / beta, w, V);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
-    int k_done = 0;
-    for (int k = 0; k < m; ++k) {
-      double *vk = V_.p + (size_t)k * ld;
-      if (transpose)
-        precond_T(vk, z_.p);
-      else
-        launch_precond(s_, N, diag_.p, o.eps_in / o.eps_out, vk, z_.p);
-      op(z_.p, w_.p, false);
-      // CGS2
-      launch_mdot(s_, n, k + 1, V_.p, ld, w_.p, partial_.p, hbuf_.p);
-      launch_gemv_sub(s_, n, k + 1, V_.p, ld, hbuf_.p, w_.p);
-      launch_mdot(s_, n, k + 1, V_.p, ld, w_.p, partial_.p, hbuf_.p + (m + 2));
-      launch_gemv_sub(s_, n, k + 1, V_.p, ld, hbuf_.p + (m + 2), w_.p);
-      launch_mdot(s_, n, 1, w_.p, ld, w_.p, partial_.p, hbuf_.p + 2 * (m + 2));
-      PBMP_HIP(hipMemcpyAsync(hh.data(), hbuf_.p, sizeof(double) * 3 * (m + 2),
+    const double target = 0.5 * o.gmres_tol * bnorm;
+    const int kmax = std::min(m, o.gmres_maxit - it);
+    auto enqueue = [&](int k) {
+      prec(V + (size_t)k * ld, z);
+      op(z, w, false);
+      // CGS2: h1 = V^T w, w -= V h1, h2 = V^T w, w -= V h2, |w|^2; the
+      // totals land in hbuf (h1, h2, |w|^2) for the host
+      int nb = launch_mdot_partial(s_, n, k + 1, V, ld, w, partial_.p);
+      launch_gemv_sub_p(s_, n, k + 1, V, ld, nb, partial_.p, hbuf_.p, w);
+      nb = launch_mdot_partial(s_, n, k + 1, V, ld, w, partial_.p);
+      launch_gemv_sub_p(s_, n, k + 1, V, ld, nb, partial_.p, hbuf_.p + (m + 2), w);
+      nb = launch_mdot_partial(s_, n, 1, w, ld, w, partial_.p);
+      launch_scale_inv_sqrt_p(s_, n, nb, partial_.p, hbuf_.p + 2 * (m + 2), w,
+                              V + (size_t)(k + 1) * ld);
+      PBMP_HIP(hipMemcpyAsync(hpin_ + k * stride, hbuf_.p, sizeof(double) * stride,
                               hipMemcpyDeviceToHost, s_));
-      sync();
+      PBMP_HIP(hipEventRecord(kev_[k], s_));
+      ++gmres_iters_;
+    };
+    enqueue(0);
+    int enq = 1, done = 0;
+    double last = beta;
+    while (true) {
+      const double rho = std::min({ratio[0], ratio[1], ratio[2], 1.0});
+      if (enq == done + 1 && enq < kmax && last * rho > target) enqueue(enq++);
+      PBMP_HIP(hipEventSynchronize(kev_[done]));
+      const double *hh = hpin_ + done * stride;
+      const int k = done;
       for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = hh[i] + hh[m + 2 + i];
       const double hn = std::sqrt(hh[2 * (m + 2)]);
       H[(size_t)(k + 1) * m + k] = hn;
-      if (hn > 0) launch_scale_inv_sqrt(s_, n, w_.p, hbuf_.p + 2 * (m + 2), V_.p + (size_t)(k + 1) * ld);
       for (int i = 0; i < k; ++i) {
         const double a = H[(size_t)i * m + k], bb = H[(size_t)(i + 1) * m + k];
         H[(size_t)i * m + k] = cs[i] * a + sn[i] * bb;
@@ -687,136 +728,84 @@ int Runtime::gmres(const double *b, double *x, bool transpose, int *iters) {
       g[k + 1] = -sn[k] * g[k];
       g[k] = cs[k] * g[k];
       ++it;
-      ++gmres_iters_;
-      k_done = k + 1;
-      if (std::fabs(g[k + 1]) <= 0.5 * o.gmres_tol * bnorm || it >= o.gmres_maxit || hn == 0.0)
-        break;
+      done = k + 1;
+      const double res = std::fabs(g[k + 1]);
+      if (last > 0.0) {
+        ratio[2] = ratio[1];
+        ratio[1] = ratio[0];
+        ratio[0] = res / last;
+      }
+      last = res;
+      if (res <= target || hn == 0.0 || done >= kmax) break;
+      if (enq == done) enqueue(enq++);
     }
+    const int k_done = done;
     for (int i = k_done - 1; i >= 0; --i) {
       double sacc = g[i];
       for (int j = i + 1; j < k_done; ++j) sacc -= H[(size_t)i * m + j] * y[j];
       y[i] = sacc / H[(size_t)i * m + i];
     }
-    PBMP_HIP(hipMemcpyAsync(ybuf_.p, y.data(), sizeof(double) * k_done,
-                            hipMemcpyHostToDevice, s_));
+    update(k_done, y.data());
+    *iters = it;
+  }
+}
+
+int Runtime::gmres(const double *b, double *x, bool transpose, int *iters) {
+  const int N = N_, n = 2 * N;
+  const size_t ld = n;
+  KOp op = [&](const double *in, double *out, bool f64) {
+    if (transpose) apply_transpose(in, out, f64);
+    else apply(in, out, f64);
+  };
+  KPrec prec = [&](const double *u, double *zz) {
+    if (transpose) precond_T(u, zz);
+    else launch_precond(s_, N, diag_.p, o.eps_in / o.eps_out, u, zz);
+  };
+  KUpdate update = [&](int k_done, const double *y) {
     if (transpose) {
-      // x += M^{-T} (V y)
-      for (int i = 0; i < k_done; ++i) y[i] = -y[i];
-      PBMP_HIP(hipMemcpyAsync(ybuf_.p, y.data(), sizeof(double) * k_done,
+      // x += M^{-T} (V y): ax = 0 - V (-y), then the preconditioner
+      std::vector<double> ny(y, y + k_done);
+      for (double &v : ny) v = -v;
+      PBMP_HIP(hipMemcpyAsync(ybuf_.p, ny.data(), sizeof(double) * k_done,
                               hipMemcpyHostToDevice, s_));
-      PBMP_HIP(hipMemsetAsync(ax_.p, 0, sizeof(double) * n, s_));
+      launch_scale(s_, n, 0.0, ax_.p, ax_.p);
       launch_gemv_sub(s_, n, k_done, V_.p, ld, ybuf_.p, ax_.p);
       precond_T(ax_.p, z_.p);
       launch_axpy(s_, n, 1.0, z_.p, x);
       sync();
     } else {
+      PBMP_HIP(hipMemcpyAsync(ybuf_.p, y, sizeof(double) * k_done, hipMemcpyHostToDevice,
+                              s_));
       launch_update_solution(s_, N, k_done, V_.p, ld, ybuf_.p, diag_.p,
                              o.eps_in / o.eps_out, x);
     }
-    *iters = it;
-  }
+  };
+  return gmres_core(n, op, prec, update, b, x, V_.p, w_.p, z_.p, ax_.p, iters);
 }
 
 // GMRES for a general operator of size n (right preconditioning, CGS2,
-// Givens on the host, FP64 refinement as in gmres).  x holds the initial
-// guess.
-int Runtime::gmres_generic(int n, const std::function<void(const double *, double *, bool)> &op,
-                           const std::function<void(const double *, double *)> &prec,
-                           const double *b, double *x, int *iters) {
+// FP64 refinement as in gmres).  x holds the initial guess.
+int Runtime::gmres_generic(int n, const KOp &op, const KPrec &prec, const double *b, double *x,
+                           int *iters) {
   const int m = o.gmres_restart;
   const size_t ld = n;
   gV_.reserve((size_t)(m + 1) * n);
   gw_.reserve(n);
   gz_.reserve(n);
   gax_.reserve(n);
-  auto dot_host = [&](const double *a, const double *bb) {
-    launch_mdot(s_, n, 1, a, ld, bb, partial_.p, hbuf_.p);
-    double h;
-    PBMP_HIP(hipMemcpyAsync(&h, hbuf_.p, sizeof(double), hipMemcpyDeviceToHost, s_));
-    sync();
-    return h;
-  };
-  const double bnorm = std::sqrt(dot_host(b, b));
-  *iters = 0;
-  if (bnorm == 0.0) {
-    PBMP_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s_));
-    last_relres_ = 0.0;
-    return 0;
-  }
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hh(3 * (m + 2)), y(m);
-  bool refine = false;
-  double prev = 0.0;
-  int it = 0;
-  while (true) {
-    op(x, gax_.p, refine);
-    launch_xmy(s_, n, b, gax_.p, gw_.p);
-    double beta = std::sqrt(dot_host(gw_.p, gw_.p));
-    if (!refine && !fp64() && it > 0 && beta / bnorm > 0.5 * prev && beta / bnorm > o.gmres_tol) {
-      refine = true;
-      op(x, gax_.p, true);
-      launch_xmy(s_, n, b, gax_.p, gw_.p);
-      beta = std::sqrt(dot_host(gw_.p, gw_.p));
-    }
-    last_relres_ = beta / bnorm;
-    prev = last_relres_;
-    if (last_relres_ <= o.gmres_tol) return 0;
-    if (it >= o.gmres_maxit) return PBMP_WGMRES;
-    launch_scale(s_, n, 1.0 / beta, gw_.p, gV_.p);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int k_done = 0;
-    for (int k = 0; k < m; ++k) {
-      double *vk = gV_.p + (size_t)k * ld;
-      prec(vk, gz_.p);
-      op(gz_.p, gw_.p, false);
-      launch_mdot(s_, n, k + 1, gV_.p, ld, gw_.p, partial_.p, hbuf_.p);
-      launch_gemv_sub(s_, n, k + 1, gV_.p, ld, hbuf_.p, gw_.p);
-      launch_mdot(s_, n, k + 1, gV_.p, ld, gw_.p, partial_.p, hbuf_.p + (m + 2));
-      launch_gemv_sub(s_, n, k + 1, gV_.p, ld, hbuf_.p + (m + 2), gw_.p);
-      launch_mdot(s_, n, 1, gw_.p, ld, gw_.p, partial_.p, hbuf_.p + 2 * (m + 2));
-      PBMP_HIP(hipMemcpyAsync(hh.data(), hbuf_.p, sizeof(double) * 3 * (m + 2),
-                              hipMemcpyDeviceToHost, s_));
-      sync();
-      for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = hh[i] + hh[m + 2 + i];
-      const double hn = std::sqrt(hh[2 * (m + 2)]);
-      H[(size_t)(k + 1) * m + k] = hn;
-      if (hn > 0)
-        launch_scale_inv_sqrt(s_, n, gw_.p, hbuf_.p + 2 * (m + 2), gV_.p + (size_t)(k + 1) * ld);
-      for (int i = 0; i < k; ++i) {
-        const double a = H[(size_t)i * m + k], bb = H[(size_t)(i + 1) * m + k];
-        H[(size_t)i * m + k] = cs[i] * a + sn[i] * bb;
-        H[(size_t)(i + 1) * m + k] = -sn[i] * a + cs[i] * bb;
-      }
-      const double a = H[(size_t)k * m + k], bb = H[(size_t)(k + 1) * m + k];
-      const double den = std::hypot(a, bb);
-      cs[k] = den > 0 ? a / den : 1.0;
-      sn[k] = den > 0 ? bb / den : 0.0;
-      H[(size_t)k * m + k] = den;
-      H[(size_t)(k + 1) * m + k] = 0.0;
-      g[k + 1] = -sn[k] * g[k];
-      g[k] = cs[k] * g[k];
-      ++it;
-      ++gmres_iters_;
-      k_done = k + 1;
-      if (std::fabs(g[k + 1]) <= 0.5 * o.gmres_tol * bnorm || it >= o.gmres_maxit || hn == 0.0)
-        break;
-    }
-    for (int i = k_done - 1; i >= 0; --i) {
-      double sacc = g[i];
-      for (int j = i + 1; j < k_done; ++j) sacc -= H[(size_t)i * m + j] * y[j];
-      y[i] = sacc / H[(size_t)i * m + i];
-    }
+  KUpdate update = [&](int k_done, const double *y) {
     // x += M^{-1} (V y)
-    for (int i = 0; i < k_done; ++i) y[i] = -y[i];
-    PBMP_HIP(hipMemcpyAsync(ybuf_.p, y.data(), sizeof(double) * k_done, hipMemcpyHostToDevice,
+    std::vector<double> ny(y, y + k_done);
+    for (double &v : ny) v = -v;
+    PBMP_HIP(hipMemcpyAsync(ybuf_.p, ny.data(), sizeof(double) * k_done, hipMemcpyHostToDevice,
                             s_));
-    PBMP_HIP(hipMemsetAsync(gax_.p, 0, sizeof(double) * n, s_));
+    launch_scale(s_, n, 0.0, gax_.p, gax_.p);
     launch_gemv_sub(s_, n, k_done, gV_.p, ld, ybuf_.p, gax_.p);
     prec(gax_.p, gz_.p);
     launch_axpy(s_, n, 1.0, gz_.p, x);
     sync();
-    *iters = it;
-  }
+  };
+  return gmres_core(n, op, prec, update, b, x, gV_.p, gw_.p, gz_.p, gax_.p, iters);
 }
 
 // ------------------------------------------------------------- readout

@@ -152,9 +152,18 @@ class Runtime {
   void precond_stern(const double *v, double *z);
   int gmres_stern(const double *b, double *x, int *iters);
   void stern_matvec_user(const double *x, double *y, int where);
-  int gmres_generic(int n, const std::function<void(const double *, double *, bool)> &op,
-                    const std::function<void(const double *, double *)> &prec,
-                    const double *b, double *x, int *iters);
+  using KOp = std::function<void(const double *, double *, bool)>;  // y = A x (f64 flag)
+  using KPrec = std::function<void(const double *, double *)>;      // z = M^{-1} v
+  using KUpdate = std::function<void(int, const double *)>;         // x += M^{-1} V y
+  int gmres_generic(int n, const KOp &op, const KPrec &prec, const double *b, double *x,
+                    int *iters);
+  int gmres_core(int n, const KOp &op, const KPrec &prec, const KUpdate &update,
+                 const double *b, double *x, double *V, double *w, double *z, double *ax,
+                 int *iters);
+  void krylov_reserve(int n);
+  double *hpin_ = nullptr;           // pinned Hessenberg columns [m][3(m+2)]
+  size_t hpin_n_ = 0;
+  std::vector<hipEvent_t> kev_;      // one per Arnoldi step of a cycle
   friend struct Backward;
 };
 

@@ -25,10 +25,16 @@ constexpr int kM2PChunkBoxes = PBMP_M2P_CHUNK;
 constexpr int kP2PTaskWork = PBMP_P2P_WORK;
 constexpr int kM2PTaskWork = PBMP_M2P_WORK;
 // panels per moment task
-#ifndef PBMP_MOM_CHUNK
-#define PBMP_MOM_CHUNK 2048
+// Panels per moment task: one wave per task, so a slice bounds the nodes a
+// lane walks; higher orders carry a longer wave reduction per task and
+// take longer slices (measured fastest: 512 up to P = 4, 1024 above).
+#ifdef PBMP_MOM_CHUNK
+inline int mom_chunk_panels(int) { return PBMP_MOM_CHUNK; }
+#else
+inline int mom_chunk_panels(int order) { return order <= 4 ? 512 : 1024; }
 #endif
-constexpr int kMomChunkPanels = PBMP_MOM_CHUNK;
+// leaves per shift task (moments of the boxes above the leaves)
+constexpr int kShiftLeaves = 16;
 // target panels per M2P^T task (adjoint product)
 constexpr int kM2PTChunkTargets = 512;
 
@@ -73,11 +79,18 @@ class Tree {
   Dbuf<int> d_tslotsT;    // [N] transposed slots of the panel's leaf (tasks + 1)
   int n_p2pT_tasks = 0, n_m2pT_tasks = 0, max_slots_T = 1;
   Dbuf<double> d_Lpart, d_L;  // local coefficients: per M2P^T task, per box [2][ncoef]
-  // moment tasks: the panels of every accepted box in slices of at most
-  // kMomChunkPanels; task = (box, s0, s1); a box's slices are consecutive
+  // moment tasks: the panels of every leaf in slices of at most
+  // mom_chunk_panels(P); task = (box, s0, s1); a box's slices are consecutive
   int n_mom_tasks = 0;
   Dbuf<int> d_mom_task, d_mom_first, d_mom_count;
   Dbuf<double> d_mom_part;  // [n_mom_tasks][2][ncoef]
+  // shift tasks: the leaves under an accepted box with children in runs of
+  // at most kShiftLeaves; task = (box, first leaf index, end leaf index)
+  int n_shift_tasks = 0;
+  Dbuf<int> d_shift_task, d_shift_first, d_shift_count;
+  Dbuf<double> d_shift_part;  // [n_shift_tasks][2][ncoef]
+  Dbuf<int> d_shift_toff, d_shift_tjq;  // per coefficient k: terms [toff[k], toff[k+1]), (j, k-j)
+  Dbuf<double> d_shift_tc;              // C(k, j) of each term
   Dbuf<double> d_mom64;   // [nbox][2][ncoef]
   Dbuf<float> d_mom32;    // [nbox][2][ncoef]
   Dbuf<int> d_monos;      // [3*ncoef] exponents

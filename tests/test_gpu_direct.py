@@ -154,15 +154,17 @@ def test_mixed_refinement_reaches_fp64(cfg0, ragged):
     recomputing restart residuals with the FP64 product (iterative
     refinement): the mixed solve's final surface solution has an FP64
     residual far below the FP32 product's floor (~1e-7), checked with the
-    FP64 operator against the right-hand side of the returned dipoles
-    (one relaxation step, under 1e-10 D, after the last solve's).  The
-    energy still carries the FP32 far field of the site readout (1e-7)."""
+    FP64 operator against the mixed path's own right-hand side (FP32 pair
+    terms) for the returned dipoles (one relaxation step, under 1e-10 D,
+    after the last solve's).  The energy still carries the FP32 pair terms
+    of the right-hand side and the site readout (1e-7)."""
     for w in (cfg0, ragged):
         kw = dict(gmres_tol=1e-11, scf_tol_debye=1e-10, scf_maxit=500)
-        got = _solver(w, precision="mixed", **kw).solve()
+        smx = _solver(w, precision="mixed", **kw)
+        got = smx.solve()
         s64 = _solver(w, precision="fp64", **kw)
         x = np.concatenate([got["phi"], got["dphidn"]]) / (4 * np.pi)
-        f = s64.rhs(w["d"] + got["mu_diss"])
+        f = smx.rhs(w["d"] + got["mu_diss"])
         b = np.concatenate([f, np.zeros_like(f)])
         res = np.linalg.norm(b - s64.matvec(x)) / np.linalg.norm(b)
         ref = s64.solve()
