@@ -96,7 +96,9 @@ typedef struct pbmp_options {
                            dipole loops from the previous solve's surface
                            solution and dipoles (same mesh and site count;
                            sites may have moved), e.g. for nearby geometries
-                           in finite differences or dynamics; 0: from zero */
+                           in finite differences or dynamics, and a backward
+                           starts its transposed loops from the previous
+                           backward's multipliers; 0: from zero */
 } pbmp_options;
 
 typedef struct pbmp_ctx pbmp_ctx;
@@ -146,9 +148,13 @@ int pbmp_create(const pbmp_options *o, pbmp_ctx **out);
 
 /* Change the solver settings of an existing context between solves:
  * gmres_restart, gmres_tol, gmres_maxit, scf_tol_debye, scf_omega,
- * scf_maxit and warm_start are taken from *o (range-checked as in
- * pbmp_create); every other field must equal the context's (PBMP_EARG
- * otherwise: the discretisation is fixed at creation). */
+ * scf_maxit, warm_start and precision are taken from *o (range-checked as
+ * in pbmp_create); every other field must equal the context's (PBMP_EARG
+ * otherwise: the discretisation is fixed at creation).  A precision change
+ * keeps the last solution, so a backward may run at another precision than
+ * the solve it differentiates (e.g. an FP64 state with mixed-precision
+ * adjoint solves, whose FP64 refinement keeps them at the GMRES tolerance);
+ * not available with a Stern layer (PBMP_EARG). */
 int pbmp_set_options(pbmp_ctx *c, const pbmp_options *o);
 
 /* Set the surface mesh: nv vertices [nv*3] (x,y,z per vertex, row-major),

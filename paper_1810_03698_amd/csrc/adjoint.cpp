@@ -85,7 +85,14 @@ int Runtime::backward(double dGbar, double *g_xyz, double *g_q, double *g_d, dou
   const int M = M_, N = N_;
   const double c = dGbar * coulomb_kcal() * 0.5;
   const double ta = o.thole_a, eps = o.eps_in;
-  Dbuf<double> Wc, Wp, Jmu, lv, ld, wv, wd, E, F, sig, lx, rhs, red;
+  Dbuf<double> Wc, Wp, Jmu, wv, wd, E, F, sig, rhs, red;
+  // multipliers, kept on the context: with warm_start a backward starts
+  // from the previous backward's (same mesh and site count), rescaled to
+  // this dG_bar
+  Dbuf<double> &lv = adj_lv_, &ld = adj_ld_, &lx = adj_lx_;
+  const bool warm = o.warm_start && adj_ok_ && adj_M_ == M && adj_bar_ != 0.0 &&
+                    lx.n == 2 * (size_t)N;
+  adj_ok_ = false;
   Wc.alloc(10 * (size_t)M);
   Wp.alloc(10 * (size_t)M);
   Jmu.alloc(3 * (size_t)M);
@@ -99,6 +106,12 @@ int Runtime::backward(double dGbar, double *g_xyz, double *g_q, double *g_d, dou
   lx.alloc(2 * (size_t)N);
   rhs.alloc(2 * (size_t)N);
   red.alloc(2);
+  if (warm && dGbar != adj_bar_) {
+    const double f = dGbar / adj_bar_;
+    launch_scale(s_, 3 * M, f, lv.p, lv.p);
+    launch_scale(s_, 3 * M, f, ld.p, ld.p);
+    launch_scale(s_, 2 * N, f, lx.p, lx.p);
+  }
   launch_make_weights(s_, M, c, sq_.p, sd_.p, sQ_.p, nullptr, Wc.p);
   launch_jmu(s_, M, Wc.p, sxyz_.p, salpha_.p, ta, eps, Jmu.p);
   // the relaxed transposed loops stop at a relative change of a tenth of
@@ -107,8 +120,10 @@ int Runtime::backward(double dGbar, double *g_xyz, double *g_q, double *g_d, dou
   const double rel_tol = std::min(1e-7, std::max(1e-11, 0.1 * o.gmres_tol));
   int warn = 0;
   auto relax = [&](bool dissolved, Dbuf<double> &lam, Dbuf<double> &w) {
-    PBMP_HIP(hipMemsetAsync(lam.p, 0, sizeof(double) * 3 * M, s_));
-    if (dissolved) PBMP_HIP(hipMemsetAsync(lx.p, 0, sizeof(double) * 2 * N, s_));
+    if (!warm) {
+      PBMP_HIP(hipMemsetAsync(lam.p, 0, sizeof(double) * 3 * M, s_));
+      if (dissolved) PBMP_HIP(hipMemsetAsync(lx.p, 0, sizeof(double) * 2 * N, s_));
+    }
     for (int it = 1; it <= o.scf_maxit; ++it) {
       launch_scale_sites(s_, M, salpha_.p, lam.p, w.p);
       if (dissolved) {
@@ -219,6 +234,9 @@ int Runtime::backward(double dGbar, double *g_xyz, double *g_q, double *g_d, dou
   put(g_Q, oQ);
   put(g_verts, overts);
   sync();
+  adj_ok_ = true;
+  adj_bar_ = dGbar;
+  adj_M_ = M;
   return warn;
 }
 

@@ -305,43 +305,8 @@ __global__ __launch_bounds__(kShiftThreads) void k_shift_tasks(
 // shuffles in a fixed order.  G and TPT are chosen per task to use the most
 // lanes.  Tile, TPT bound and the use of groups are compile-time settings
 // (the defaults were the fastest measured; M2P runs without groups).
-#ifndef PBMP_P2P_TILE
-#define PBMP_P2P_TILE 128
-#endif
-#ifndef PBMP_P2P_MAXTPT
-#define PBMP_P2P_MAXTPT 5
-#endif
-#ifndef PBMP_P2P_GROUPS
-#define PBMP_P2P_GROUPS 1
-#endif
-#ifndef PBMP_M2P_GROUPS
-#define PBMP_M2P_GROUPS 0
-#endif
 constexpr int kTileT = PBMP_P2P_TILE;
 constexpr int kMaxTPT = PBMP_P2P_MAXTPT;
-
-struct LaneSplit {
-  int G, L, tpt;
-};
-
-// G, L = 64 / G and targets per lane for nt targets: maximise the useful
-// fraction G nt / (64 tpt) with tpt <= kMaxTPT (ties: fewer groups; a
-// leaf of more than 64 kMaxTPT targets takes several passes with G = 1)
-__device__ inline LaneSplit lane_split(int nt) {
-  LaneSplit best{1, 64, min(kMaxTPT, (nt + 63) / 64)};
-  float be = (float)nt / (64.0f * best.tpt * ((nt + 64 * best.tpt - 1) / (64 * best.tpt)));
-  for (int G = 2; G <= 16 * PBMP_P2P_GROUPS; ++G) {
-    const int L = 64 / G;
-    const int tpt = (nt + L - 1) / L;
-    if (tpt > kMaxTPT) continue;
-    const float e = (float)(G * nt) / (64.0f * tpt);
-    if (e > be) {
-      be = e;
-      best = LaneSplit{G, L, tpt};
-    }
-  }
-  return best;
-}
 
 // Copies nj (<= MAXREC) records of 16 T from global memory to LDS in
 // 16-byte accesses, every load of the lane issued before the first store

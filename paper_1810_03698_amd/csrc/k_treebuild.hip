@@ -261,6 +261,18 @@ struct ListOut {
   int *slots_of_box;
 };
 
+// P2P task of one source run [sb, se) of sub-ranges over the leaf's
+// targets, writing slot `slot`
+__device__ inline void emit_p2p(const ListOut &out, int at, int slot, int t0, int t1, int sb,
+                                int se) {
+  int *tk = out.ptask + 4 * at;
+  tk[0] = t0;
+  tk[1] = t1;
+  tk[2] = sb;
+  tk[3] = se;
+  out.pslot[at] = slot;
+}
+
 template <bool FILL>
 __global__ void k_lists(int nleaf, const int *__restrict__ leaves, Boxes b,
                         const double *__restrict__ center, const double *__restrict__ radius,
@@ -275,7 +287,7 @@ __global__ void k_lists(int nleaf, const int *__restrict__ leaves, Boxes b,
   // task and become sources per task for this leaf's size
   chunk = task_chunk(chunk, t1 - t0, kMinChunk, kMaxChunk);
   mchunk = task_chunk(mchunk, t1 - t0, 1, kM2PChunkBoxes);
-  int nm = 0, np = 0, nsub = 0, ntask = 0, cnt = 0, panels = 0;
+  int nm = 0, np = 0, nsub = 0, ntask = 0, nemit = 0, cnt = 0, panels = 0;
   int om = 0, op = 0, os = 0, ot = 0, firstsub = 0;
   if (FILL) {
     om = out.off_m2p[li];
@@ -315,14 +327,10 @@ __global__ void k_lists(int nleaf, const int *__restrict__ leaves, Boxes b,
         cnt += take;
         if (cnt == chunk) {
           if (FILL) {
-            int *tk = out.ptask + 4 * (ot + ntask);
-            tk[0] = t0;
-            tk[1] = t1;
-            tk[2] = firstsub;
-            tk[3] = os + nsub;
-            out.pslot[ot + ntask] = ntask;
+            emit_p2p(out, ot + nemit, ntask, t0, t1, firstsub, os + nsub);
             firstsub = os + nsub;
           }
+          ++nemit;
           ++ntask;
           cnt = 0;
         }
@@ -332,14 +340,8 @@ __global__ void k_lists(int nleaf, const int *__restrict__ leaves, Boxes b,
     }
   }
   if (cnt > 0) {
-    if (FILL) {
-      int *tk = out.ptask + 4 * (ot + ntask);
-      tk[0] = t0;
-      tk[1] = t1;
-      tk[2] = firstsub;
-      tk[3] = os + nsub;
-      out.pslot[ot + ntask] = ntask;
-    }
+    if (FILL) emit_p2p(out, ot + nemit, ntask, t0, t1, firstsub, os + nsub);
+    ++nemit;
     ++ntask;
   }
   const int nmt = (nm + mchunk - 1) / mchunk;
@@ -359,11 +361,11 @@ __global__ void k_lists(int nleaf, const int *__restrict__ leaves, Boxes b,
     c[0] = nm;
     c[1] = np;
     c[2] = nsub;
-    c[3] = ntask;
+    c[3] = nemit;
     c[4] = nmt;
     c[5] = panels;
     c[6] = t1 - t0;
-    c[7] = 0;
+    c[7] = ntask;
   }
 }
 
@@ -740,7 +742,7 @@ void Tree::build_device(int N, int nf, const uint64_t *key, const double *geo,
     const int *c = &h[8 * (size_t)k];
     direct_pairs += (double)c[6] * c[5] * nf;
     m2p_pairs += (double)c[6] * c[0];
-    max_slots = std::max(max_slots, c[3] + c[4]);
+    max_slots = std::max(max_slots, c[7] + c[4]);
   }
   // moment tasks for the boxes that some leaf accepts
   {

@@ -210,9 +210,12 @@ void Runtime::set_options(const pbmp_options &n) {
   PBMP_REQUIRE(n.eps_in == o.eps_in && n.eps_out == eout && n.kappa == kap &&
                    n.gauss_far == o.gauss_far && n.near_eta == o.near_eta &&
                    n.mode == o.mode && n.theta == o.theta && n.order_P == o.order_P &&
-                   n.leaf_panels == o.leaf_panels && n.thole_a == o.thole_a &&
-                   n.precision == o.precision,
-               PBMP_EARG, "only the solver settings can change on a context");
+                   n.leaf_panels == o.leaf_panels && n.thole_a == o.thole_a,
+               PBMP_EARG, "only the solver settings and the precision can change on a context");
+  PBMP_REQUIRE(n.precision == PBMP_FP64 || n.precision == PBMP_MIXED, PBMP_EARG,
+               "precision must be PBMP_FP64 or PBMP_MIXED");
+  PBMP_REQUIRE(n.precision == o.precision || !outer_, PBMP_EARG,
+               "the precision of a context with a Stern layer is fixed");
   PBMP_REQUIRE(n.gmres_restart >= 1 && n.gmres_restart <= 200, PBMP_EARG,
                "gmres_restart in 1..200");
   PBMP_REQUIRE(n.gmres_tol > 0 && n.gmres_maxit >= 1, PBMP_EARG,
@@ -221,6 +224,8 @@ void Runtime::set_options(const pbmp_options &n) {
                "scf_tol_debye > 0, scf_maxit >= 1");
   PBMP_REQUIRE(n.scf_omega > 0 && n.scf_omega < 2, PBMP_EARG, "scf_omega in (0,2)");
   const bool restart_changed = n.gmres_restart != o.gmres_restart;
+  const bool precision_changed = n.precision != o.precision;
+  o.precision = n.precision;
   o.gmres_restart = n.gmres_restart;
   o.gmres_tol = n.gmres_tol;
   o.gmres_maxit = n.gmres_maxit;
@@ -233,7 +238,13 @@ void Runtime::set_options(const pbmp_options &n) {
     outer_->o.gmres_tol = n.gmres_tol;
     outer_->o.gmres_maxit = n.gmres_maxit;
   }
-  if (restart_changed && N_ > 0) {
+  if (precision_changed && N_ > 0) {
+    // the near corrections remove the far rule as the product of this
+    // precision evaluates it; the solution and dipoles stay (a backward may
+    // follow a solve at the other precision)
+    near_values();
+    alloc_work();
+  } else if (restart_changed && N_ > 0) {
     alloc_work();
     if (outer_)
       partial_.reserve((size_t)(o.gmres_restart + 2) * ((sX_.n + 4095) / 4096 + 1));
@@ -257,6 +268,8 @@ void Runtime::sync() { PBMP_HIP(hipStreamSynchronize(s_)); }
 void Runtime::set_mesh(int64_t nv, const double *verts, int64_t nt,
                        const int32_t *tris, int where) {
   auto t0 = clk::now();
+  ax_holds_x_ = gax_holds_x_ = false;
+  adj_ok_ = false;
   PBMP_REQUIRE(nv >= 4 && nt >= 4 && nt < (1 << 28) && nv < (1 << 28), PBMP_EARG,
                "mesh sizes out of range");
   PBMP_REQUIRE(where == PBMP_HOST || where == PBMP_DEVICE, PBMP_EARG, "bad where");
@@ -400,17 +413,7 @@ void Runtime::build_near_lists() {
   nnz_ = (int)col.size();
   nval_.alloc(4 * col.size());
   diag_.alloc(2 * (size_t)N);
-  launch_near_values(s_, fp64(), N, nrow_.p, ncol_.p, verts_.p, tri_.p, geo_.p,
-                     src64_.p, src32_.p, tgt32_.p, ru_, o.kappa, nval_.p, diag_.p);
-  if (!fp64()) {
-    // corrections against the FP64 far field, for the FP64 residual
-    // products of the refinement in GMRES
-    nval64_.alloc(4 * col.size());
-    launch_near_values(s_, true, N, nrow_.p, ncol_.p, verts_.p, tri_.p, geo_.p, src64_.p,
-                       src32_.p, tgt32_.p, ru_, o.kappa, nval64_.p, diag_.p);
-  } else {
-    nval64_.release();
-  }
+  near_values();
   // transposed structure: for column j, the entry ids e with col[e] == j
   std::vector<int> trow(N + 1, 0), tent(col.size()), tcol(col.size());
   for (int c : col) trow[c + 1]++;
@@ -428,7 +431,24 @@ void Runtime::build_near_lists() {
   sync();
 }
 
+// near/self correction values for the current precision (and, in mixed
+// precision, against the FP64 far field for the refinement's products)
+void Runtime::near_values() {
+  const int N = N_;
+  launch_near_values(s_, fp64(), N, nrow_.p, ncol_.p, verts_.p, tri_.p, geo_.p,
+                     src64_.p, src32_.p, tgt32_.p, ru_, o.kappa, nval_.p, diag_.p);
+  if (!fp64()) {
+    nval64_.alloc(nval_.n);
+    launch_near_values(s_, true, N, nrow_.p, ncol_.p, verts_.p, tri_.p, geo_.p, src64_.p,
+                       src32_.p, tgt32_.p, ru_, o.kappa, nval64_.p, diag_.p);
+  } else {
+    nval64_.release();
+  }
+  sync();
+}
+
 void Runtime::alloc_work() {
+  ax_holds_x_ = gax_holds_x_ = false;
   const int N = N_;
   const int n = 2 * N;
   const int m = o.gmres_restart;
@@ -638,7 +658,12 @@ void Runtime::krylov_reserve(int n) {
 
 int Runtime::gmres_core(int n, const KOp &op, const KPrec &prec, const KUpdate &update,
                         const double *b, double *x, double *V, double *w, double *z,
-                        double *ax, int *iters) {
+                        double *ax, int *iters, bool *ax_valid) {
+  // ax_valid (may be null): in, ax already holds op(x) for this x (the last
+  // residual product of the previous solve, x unchanged since), so the first
+  // residual needs no product; out, whether ax holds op(x) on return
+  bool have_ax = ax_valid && *ax_valid;
+  if (ax_valid) *ax_valid = false;
   const int m = o.gmres_restart;
   const size_t ld = n;
   const size_t stride = 3 * (size_t)(m + 2);
@@ -667,7 +692,8 @@ int Runtime::gmres_core(int n, const KOp &op, const KPrec &prec, const KUpdate &
   double ratio[3] = {0.1, 0.1, 0.1};
   int it = 0;
   while (true) {
-    op(x, ax, refine);
+    if (!have_ax) op(x, ax, refine);
+    have_ax = false;
     launch_xmy(s_, n, b, ax, w);
     double beta = std::sqrt(dot_host(w, w));
     if (!refine && !fp64() && it > 0 && beta / bnorm > 0.5 * prev && beta / bnorm > o.gmres_tol) {
@@ -678,8 +704,10 @@ int Runtime::gmres_core(int n, const KOp &op, const KPrec &prec, const KUpdate &
     }
     last_relres_ = beta / bnorm;
     prev = last_relres_;
-    if (last_relres_ <= o.gmres_tol) return 0;
-    if (it >= o.gmres_maxit) return PBMP_WGMRES;
+    if (last_relres_ <= o.gmres_tol || it >= o.gmres_maxit) {
+      if (ax_valid) *ax_valid = true;
+      return last_relres_ <= o.gmres_tol ? 0 : PBMP_WGMRES;
+    }
     launch_scale(s_, n, 1.0 / beta, w, V);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
@@ -780,13 +808,16 @@ int Runtime::gmres(const double *b, double *x, bool transpose, int *iters) {
                              o.eps_in / o.eps_out, x);
     }
   };
-  return gmres_core(n, op, prec, update, b, x, V_.p, w_.p, z_.p, ax_.p, iters);
+  // the forward solve of the SCF loop reuses A x_ from the previous solve
+  bool *valid = (!transpose && x == x_.p) ? &ax_holds_x_ : nullptr;
+  if (!valid) ax_holds_x_ = false;  // ax_ is overwritten
+  return gmres_core(n, op, prec, update, b, x, V_.p, w_.p, z_.p, ax_.p, iters, valid);
 }
 
 // GMRES for a general operator of size n (right preconditioning, CGS2,
 // FP64 refinement as in gmres).  x holds the initial guess.
 int Runtime::gmres_generic(int n, const KOp &op, const KPrec &prec, const double *b, double *x,
-                           int *iters) {
+                           int *iters, bool *ax_valid) {
   const int m = o.gmres_restart;
   const size_t ld = n;
   gV_.reserve((size_t)(m + 1) * n);
@@ -805,7 +836,7 @@ int Runtime::gmres_generic(int n, const KOp &op, const KPrec &prec, const double
     launch_axpy(s_, n, 1.0, gz_.p, x);
     sync();
   };
-  return gmres_core(n, op, prec, update, b, x, gV_.p, gw_.p, gz_.p, gax_.p, iters);
+  return gmres_core(n, op, prec, update, b, x, gV_.p, gw_.p, gz_.p, gax_.p, iters, ax_valid);
 }
 
 // ------------------------------------------------------------- readout
@@ -829,6 +860,7 @@ int Runtime::scf(bool solvent, double *mu, int *gm_warn) {
     if (!warm) {
       PBMP_HIP(hipMemsetAsync(x_.p, 0, sizeof(double) * 2 * N, s_));
       if (outer_) PBMP_HIP(hipMemsetAsync(sX_.p, 0, sizeof(double) * sX_.n, s_));
+      ax_holds_x_ = gax_holds_x_ = false;
     }
   }
   for (int it = 1; it <= o.scf_maxit; ++it) {

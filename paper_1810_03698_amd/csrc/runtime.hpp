@@ -120,6 +120,7 @@ class Runtime {
 
   void sync();
   void build_near_lists();
+  void near_values();
   void build_site_lists();
   void alloc_work();
   // y = A x (internal order, device)
@@ -156,10 +157,19 @@ class Runtime {
   using KPrec = std::function<void(const double *, double *)>;      // z = M^{-1} v
   using KUpdate = std::function<void(int, const double *)>;         // x += M^{-1} V y
   int gmres_generic(int n, const KOp &op, const KPrec &prec, const double *b, double *x,
-                    int *iters);
+                    int *iters, bool *ax_valid = nullptr);
   int gmres_core(int n, const KOp &op, const KPrec &prec, const KUpdate &update,
                  const double *b, double *x, double *V, double *w, double *z, double *ax,
-                 int *iters);
+                 int *iters, bool *ax_valid);
+  // ax_ = A x_ (gax_ = A sX_ for the layer system): the residual product of
+  // the last solve, valid while neither x nor the operator changed
+  bool ax_holds_x_ = false, gax_holds_x_ = false;
+  // adjoint multipliers of the last backward (vacuum and dissolved dipole
+  // loops, surface) for warm-started backward calls
+  Dbuf<double> adj_lv_, adj_ld_, adj_lx_;
+  bool adj_ok_ = false;
+  double adj_bar_ = 0.0;
+  int adj_M_ = 0;
   void krylov_reserve(int n);
   double *hpin_ = nullptr;           // pinned Hessenberg columns [m][3(m+2)]
   size_t hpin_n_ = 0;

@@ -47,6 +47,8 @@ void Runtime::probe(const double *x, bool f64, double *out4) {
 
 void Runtime::set_stern(int64_t nv, const double *verts, int64_t nt, const int32_t *tris,
                         double eps_stern, int where) {
+  ax_holds_x_ = gax_holds_x_ = false;
+  adj_ok_ = false;
   PBMP_REQUIRE(N_ > 0, PBMP_ESTATE, "set_mesh must precede pbmp_set_stern");
   if (nt == 0) {
     if (outer_) {
@@ -140,7 +142,8 @@ int Runtime::gmres_stern(const double *b, double *x, int *iters) {
   PBMP_HIP(hipMemcpyAsync(sB_.p, b, sizeof(double) * 2 * N1, hipMemcpyDeviceToDevice, s_));
   const int rc = gmres_generic(
       (int)n, [&](const double *in, double *out, bool f64) { apply_stern(in, out, f64); },
-      [&](const double *in, double *out) { precond_stern(in, out); }, sB_.p, sX_.p, iters);
+      [&](const double *in, double *out) { precond_stern(in, out); }, sB_.p, sX_.p, iters,
+      &gax_holds_x_);
   PBMP_HIP(hipMemcpyAsync(x, sX_.p, sizeof(double) * 2 * N1, hipMemcpyDeviceToDevice, s_));
   return rc;
 }

@@ -8,6 +8,45 @@
 
 namespace pbmp {
 
+// P2P tasks: source tile in LDS, targets per lane bound, lane groups on/off
+#ifndef PBMP_P2P_TILE
+#define PBMP_P2P_TILE 128
+#endif
+#ifndef PBMP_P2P_MAXTPT
+#define PBMP_P2P_MAXTPT 5
+#endif
+#ifndef PBMP_P2P_GROUPS
+#define PBMP_P2P_GROUPS 1
+#endif
+#ifndef PBMP_M2P_GROUPS
+#define PBMP_M2P_GROUPS 0
+#endif
+
+struct LaneSplit {
+  int G, L, tpt;
+};
+
+// Lanes of a one-wave P2P task for nt targets: G groups of L = 64 / G lanes,
+// tpt targets per lane, maximising the useful fraction G nt / (64 tpt) with
+// tpt <= PBMP_P2P_MAXTPT (ties: fewer groups; more than 64 * MAXTPT
+// targets take several passes with G = 1)
+__host__ __device__ inline LaneSplit lane_split(int nt) {
+  const int t1 = (nt + 63) / 64;
+  LaneSplit best{1, 64, t1 < PBMP_P2P_MAXTPT ? t1 : PBMP_P2P_MAXTPT};
+  float be = (float)nt / (64.0f * best.tpt * ((nt + 64 * best.tpt - 1) / (64 * best.tpt)));
+  for (int G = 2; G <= 16 * PBMP_P2P_GROUPS; ++G) {
+    const int L = 64 / G;
+    const int tpt = (nt + L - 1) / L;
+    if (tpt > PBMP_P2P_MAXTPT) continue;
+    const float e = (float)(G * nt) / (64.0f * tpt);
+    if (e > be) {
+      be = e;
+      best = LaneSplit{G, L, tpt};
+    }
+  }
+  return best;
+}
+
 // boxes per M2P task (one task's moments are staged in LDS)
 #ifndef PBMP_M2P_CHUNK
 #define PBMP_M2P_CHUNK 16

@@ -220,14 +220,17 @@ class Solver:
 
     def set_options(self, **kw):
         """Change solver settings between solves (gmres_restart, gmres_tol,
-        gmres_maxit, scf_tol_debye, scf_omega, scf_maxit, warm_start)."""
+        gmres_maxit, scf_tol_debye, scf_omega, scf_maxit, warm_start,
+        precision)."""
         o = self.opts
         for k, v in kw.items():
             if k not in ("gmres_restart", "gmres_tol", "gmres_maxit", "scf_tol_debye",
-                         "scf_omega", "scf_maxit", "warm_start"):
+                         "scf_omega", "scf_maxit", "warm_start", "precision"):
                 raise ValueError("%s is fixed at creation" % k)
+            if k == "precision":
+                v = PRECISION[v] if isinstance(v, str) else int(v)
             setattr(o, k, int(v) if k in ("gmres_restart", "gmres_maxit", "scf_maxit",
-                                          "warm_start") else float(v))
+                                          "warm_start", "precision") else float(v))
         self._check(self.lib.pbmp_set_options(self.ctx, ctypes.byref(o)))
 
     def set_stern(self, verts, tris, eps_stern):

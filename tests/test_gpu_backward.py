@@ -137,6 +137,47 @@ def test_backward_mixed_matches_fp64(cfg0, cfg0_grad):
         assert err < 1e-4, k
 
 
+def test_backward_mixed_adjoint_of_fp64_state(cfg0, cfg0_grad):
+    """An FP64 solve differentiated with mixed-precision adjoint solves (the
+    precision switched between solve and backward): the FP64 refinement of
+    the transposed solves keeps the gradient at FP64 quality.  Switching
+    back to FP64 reproduces the FP64 solve exactly."""
+    from paper_1810_03698_amd import Solver
+    r64, g64 = cfg0_grad
+    s = Solver(mode="direct", precision="fp64", gmres_tol=1e-13, scf_tol_debye=1e-12,
+               scf_maxit=500)
+    s.set_mesh(cfg0["verts"], cfg0["tris"])
+    s.set_sites(cfg0["xyz"], cfg0["q"], cfg0["d"], cfg0["Q9"], cfg0["alpha"])
+    r = s.solve(outputs=False)
+    assert r["dG"] == r64["dG"]
+    s.set_options(precision="mixed", gmres_tol=1e-12)
+    g = s.backward(1.0, verts=False)
+    for k in ("xyz", "q", "d", "Q9"):
+        err = np.abs(g[k] - g64[k]).max() / np.abs(g64[k]).max()
+        print("mixed adjoint of the fp64 state", k, err)
+        assert err < 1e-9, k
+    s.set_options(precision="fp64", gmres_tol=1e-13)
+    assert s.solve(outputs=False)["dG"] == r64["dG"]
+
+
+def test_backward_warm_start(cfg0, cfg0_grad):
+    """A warm-started backward (multipliers of the previous call, rescaled
+    to the new dG_bar) gives the cold gradient."""
+    from paper_1810_03698_amd import Solver
+    r64, g64 = cfg0_grad
+    s = Solver(mode="direct", precision="fp64", gmres_tol=1e-13, scf_tol_debye=1e-12,
+               scf_maxit=500, warm_start=True)
+    s.set_mesh(cfg0["verts"], cfg0["tris"])
+    s.set_sites(cfg0["xyz"], cfg0["q"], cfg0["d"], cfg0["Q9"], cfg0["alpha"])
+    s.solve(outputs=False)
+    s.backward(1.0, verts=False)
+    g = s.backward(2.0, verts=False)
+    for k in ("xyz", "q", "d", "Q9"):
+        err = np.abs(g[k] - 2.0 * g64[k]).max() / np.abs(2.0 * g64[k]).max()
+        print("warm backward", k, err)
+        assert err < 1e-10, k
+
+
 def test_backward_ragged_positions_fd():
     from tests.test_gpu_direct import _ragged
     w = _ragged()

@@ -169,11 +169,12 @@ def test_tree_lists_match_oracle(name, leaf, theta, sph5120):
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 2e-5)])
-def test_tree_transpose_is_exact_adjoint(precision, tol, sph5120):
+@pytest.mark.parametrize("P", [4, 5, 6])
+def test_tree_transpose_is_exact_adjoint(precision, tol, P, sph5120):
     """The treecode's transposed product (P2P^T, M2P^T, L2L, L2P, transposed
     corrections) is the exact transpose of its forward product:
-    <z, A x> = <A^T z, x> up to rounding."""
-    s = _solver(sph5120, precision=precision)
+    <z, A x> = <A^T z, x> up to rounding, at every order."""
+    s = _solver(sph5120, precision=precision, order_P=P)
     rng = np.random.default_rng(31)
     N = len(sph5120["tris"])
     for _ in range(2):
@@ -200,14 +201,15 @@ def test_tree_transpose_vs_oracle(sph5120):
         assert err < 5e-4
 
 
-def test_tree_backward_matches_fd():
+@pytest.mark.parametrize("P", [4, 5])
+def test_tree_backward_matches_fd(P):
     """Site-position and multipole gradients in treecode mode against
     central differences of the treecode solve itself (the adjoint solve
     uses the exact transposed treecode product)."""
     from tests.test_gpu_direct import _ragged
     w = _ragged()
     kw = dict(precision="fp64", gmres_tol=1e-13, scf_tol_debye=1e-11, scf_maxit=500,
-              leaf_panels=50)
+              leaf_panels=50, order_P=P)
     s = _solver(w, **kw)
     s.solve(outputs=False)
     g = s.backward(1.0)
