@@ -27,14 +27,14 @@ COPY_BYTES = 256 << 20
 # HBM traffic of the dominant kernel per launch, from two rocprofv3 --pmc
 # passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean over the dispatches
 # of one solve) scaled by what the counters read for a 256 MiB copy
-# (FETCH_SIZE reads 0.5004 of the bytes read, WRITE_SIZE 1.0 of the bytes
+# (FETCH_SIZE reads 0.5001 of the bytes read, WRITE_SIZE 1.0 of the bytes
 # written).  Keyed by (mode, kernel); valid only while the sources of the
 # kernel hash to the recorded value (otherwise traffic is reported null).
 TRAFFIC = {
-    ("treecode", "p2p"): {"fetch_kib": 5637.33, "fetch_scale": 0.50006,
-                          "write_kib": 39114.76, "write_scale": 1.0, "sha": "f5ce7de506bccbda"},
-    ("direct", "p2p"): {"fetch_kib": 20980.51, "fetch_scale": 0.50008,
-                        "write_kib": 33280.0, "write_scale": 1.0, "sha": "693f91615dd1aabb"},
+    ("treecode", "p2p"): {"fetch_kib": 5843.61, "fetch_scale": 0.50006,
+                          "write_kib": 51638.60, "write_scale": 1.0, "sha": "486e9fb11d200fa2"},
+    ("direct", "p2p"): {"fetch_kib": 20980.51, "fetch_scale": 0.50006,
+                        "write_kib": 33280.0, "write_scale": 1.0, "sha": "614bbeac61608d8e"},
 }
 TRAFFIC_SOURCES = {
     ("treecode", "p2p"): ["k_tree.hip", "pair.hpp", "tree.hpp", "k_treebuild.hip"],

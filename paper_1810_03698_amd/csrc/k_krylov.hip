@@ -142,6 +142,27 @@ __global__ void k_precond(int N, const double *__restrict__ diag, double e,
   z[N + i] = z2;
 }
 
+// z = M^{-1} u (as k_precond) and the far-field strengths of z packed into
+// the source records (as k_pack_strengths): the Arnoldi step's product
+// input in one launch
+__global__ void k_precond_pack(int N, int nf, const double *__restrict__ diag, double e,
+                               const double *__restrict__ geo, const double *__restrict__ u,
+                               double *__restrict__ z, double *__restrict__ src64,
+                               float *__restrict__ src32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double z1, z2;
+  block_solve(diag[i], diag[N + i], e, u[i], u[N + i], z1, z2);
+  z[i] = z1;
+  z[N + i] = z2;
+  const double wA = geo[6 * N + i] * 0.07957747154594767 / nf;  // A / (4 pi nf)
+  const double sv = wA * z2, sk = wA * z1;
+  src64[16 * (size_t)i + 13] = sv;
+  src64[16 * (size_t)i + 14] = sk;
+  src32[16 * (size_t)i + 13] = (float)sv;
+  src32[16 * (size_t)i + 14] = (float)sk;
+}
+
 __global__ void k_update_solution(int N, int nv, const double *__restrict__ V,
                                   size_t ld, const double *__restrict__ y,
                                   const double *__restrict__ diag, double e,
@@ -241,6 +262,14 @@ void launch_xmy(hipStream_t s, int n, const double *b, const double *ax,
 void launch_precond(hipStream_t s, int N, const double *diag, double eps_ratio,
                     const double *u, double *z) {
   hipLaunchKernelGGL(k_precond, g1(N), dim3(kB), 0, s, N, diag, eps_ratio, u, z);
+  PBMP_HIP(hipGetLastError());
+}
+
+void launch_precond_pack(hipStream_t s, int N, int nf, const double *diag, double eps_ratio,
+                         const double *geo, const double *u, double *z, double *src64,
+                         float *src32) {
+  hipLaunchKernelGGL(k_precond_pack, g1(N), dim3(kB), 0, s, N, nf, diag, eps_ratio, geo, u, z,
+                     src64, src32);
   PBMP_HIP(hipGetLastError());
 }
 

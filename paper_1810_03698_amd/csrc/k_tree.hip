@@ -95,11 +95,15 @@ constexpr int kP2MThreads = PBMP_P2M_THREADS;
 constexpr int kP2MTile = 64;  // panels per LDS tile (64 and 192 nodes: multiples of 64)
 static_assert(kP2MThreads % 64 == 0 && kP2MTile % kP2MThreads == 0, "P2M tiling");
 
+// direct: every leaf is one task, so the task's sums are the leaf's moments
+// and go straight to mom64 (and mom32 when not null) instead of part
 template <int P>
 __global__ __launch_bounds__(kP2MThreads) void k_p2m_tasks(int nf, const int *__restrict__ tasks,
                                                    const double *__restrict__ center,
                                                    const double *__restrict__ src,
-                                                   double *__restrict__ part) {
+                                                   double *__restrict__ part, int direct,
+                                                   double *__restrict__ mom64,
+                                                   float *__restrict__ mom32) {
   constexpr Multi<P> mi{};
   constexpr int NC = Multi<P>::n;
   constexpr int NW = kP2MThreads / 64;
@@ -185,20 +189,28 @@ __global__ __launch_bounds__(kP2MThreads) void k_p2m_tasks(int nf, const int *__
   for (int k = threadIdx.x; k < 2 * NC; k += kP2MThreads) {
     double v = red[0][k];
     for (int w = 1; w < NW; ++w) v += red[w][k];
-    part[(size_t)blockIdx.x * 2 * NC + k] = v;
+    if (direct) {
+      mom64[(size_t)B * 2 * NC + k] = v;
+      if (mom32) mom32[(size_t)B * 2 * NC + k] = (float)v;
+    } else {
+      part[(size_t)blockIdx.x * 2 * NC + k] = v;
+    }
   }
 }
 
 // mom[B] = sum of the partial moments of B's slices, in slice order
-// (mom32: the FP32 copy the mixed-precision M2P reads, or null)
+// (mom32: the FP32 copy the mixed-precision M2P reads, or null; boxes with
+// fewer than min_tasks tasks are skipped: not this pass's, or written by
+// their single task)
 __global__ void k_mom_reduce(int nbox, int ncoef2, const int *__restrict__ first,
                              const int *__restrict__ count, const double *__restrict__ part,
-                             double *__restrict__ mom, float *__restrict__ mom32) {
+                             double *__restrict__ mom, float *__restrict__ mom32,
+                             int min_tasks) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nbox * ncoef2) return;
   const int B = e / ncoef2, k = e % ncoef2;
   const int t0 = first[B], nt = count[B];
-  if (nt == 0) return;  // not this pass's box (or not needed)
+  if (nt == 0 || nt < min_tasks) return;
   double v = 0.0;
   for (int t = t0; t < t0 + nt; ++t) v += part[(size_t)t * ncoef2 + k];
   mom[e] = v;
@@ -221,8 +233,8 @@ __global__ __launch_bounds__(kShiftThreads) void k_shift_tasks(
     const int *__restrict__ tasks, const int *__restrict__ leaves,
     const double *__restrict__ center, const int *__restrict__ monos,
     const int *__restrict__ toff, const int *__restrict__ tjq,
-    const double *__restrict__ tc, const double *__restrict__ mom,
-    double *__restrict__ part) {
+    const double *__restrict__ tc, double *__restrict__ mom, float *__restrict__ mom32,
+    const int *__restrict__ count, double *__restrict__ part) {
   constexpr int NC = (P + 1) * (P + 2) * (P + 3) / 6;
   constexpr int R = (NC + kShiftThreads - 1) / kShiftThreads;
   __shared__ double sm[kShiftLeaves * 2 * NC], sd[kShiftLeaves * NC];
@@ -290,8 +302,17 @@ __global__ __launch_bounds__(kShiftThreads) void k_shift_tasks(
         aK += w[l];
       }
     }
-    part[(size_t)blockIdx.x * 2 * NC + k] = aV;
-    part[(size_t)blockIdx.x * 2 * NC + NC + k] = aK;
+    if (count[B] == 1) {  // the box's only task: its moments
+      mom[(size_t)B * 2 * NC + k] = aV;
+      mom[(size_t)B * 2 * NC + NC + k] = aK;
+      if (mom32) {
+        mom32[(size_t)B * 2 * NC + k] = (float)aV;
+        mom32[(size_t)B * 2 * NC + NC + k] = (float)aK;
+      }
+    } else {
+      part[(size_t)blockIdx.x * 2 * NC + k] = aV;
+      part[(size_t)blockIdx.x * 2 * NC + NC + k] = aK;
+    }
   }
 }
 
@@ -684,19 +705,23 @@ template <int P>
 void launch_moments_p(Tree &t, hipStream_t s, int nf, const double *src64, float *mom32) {
   constexpr int NC = Multi<P>::n;
   if (t.n_mom_tasks == 0) return;
+  const int direct = t.n_mom_tasks == t.nleaf;  // no leaf split into slices
   hipLaunchKernelGGL(k_p2m_tasks<P>, dim3(t.n_mom_tasks), dim3(kP2MThreads), 0, s, nf,
-                     t.d_mom_task.p, t.d_center.p, src64, t.d_mom_part.p);
+                     t.d_mom_task.p, t.d_center.p, src64, t.d_mom_part.p, direct, t.d_mom64.p,
+                     mom32);
   const int n = t.nbox * 2 * NC;
-  hipLaunchKernelGGL(k_mom_reduce, dim3((n + 255) / 256), dim3(256), 0, s, t.nbox, 2 * NC,
-                     t.d_mom_first.p, t.d_mom_count.p, t.d_mom_part.p, t.d_mom64.p, mom32);
+  if (!direct)
+    hipLaunchKernelGGL(k_mom_reduce, dim3((n + 255) / 256), dim3(256), 0, s, t.nbox, 2 * NC,
+                       t.d_mom_first.p, t.d_mom_count.p, t.d_mom_part.p, t.d_mom64.p, mom32, 1);
   if (t.n_shift_tasks > 0) {
     hipLaunchKernelGGL(k_shift_tasks<P>, dim3(t.n_shift_tasks), dim3(kShiftThreads), 0, s,
                        t.d_shift_task.p, t.d_leaves.p, t.d_center.p, t.d_monos.p,
-                       t.d_shift_toff.p, t.d_shift_tjq.p, t.d_shift_tc.p, t.d_mom64.p,
-                       t.d_shift_part.p);
-    hipLaunchKernelGGL(k_mom_reduce, dim3((n + 255) / 256), dim3(256), 0, s, t.nbox, 2 * NC,
-                       t.d_shift_first.p, t.d_shift_count.p, t.d_shift_part.p, t.d_mom64.p,
-                       mom32);
+                       t.d_shift_toff.p, t.d_shift_tjq.p, t.d_shift_tc.p, t.d_mom64.p, mom32,
+                       t.d_shift_count.p, t.d_shift_part.p);
+    if (t.shift_multi)
+      hipLaunchKernelGGL(k_mom_reduce, dim3((n + 255) / 256), dim3(256), 0, s, t.nbox, 2 * NC,
+                         t.d_shift_first.p, t.d_shift_count.p, t.d_shift_part.p, t.d_mom64.p,
+                         mom32, 2);
   }
 }
 

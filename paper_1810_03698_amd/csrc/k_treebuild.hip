@@ -772,6 +772,12 @@ void Tree::build_device(int N, int nf, const uint64_t *key, const double *geo,
     hipLaunchKernelGGL(k_shift_counts, grid_for(nbox), dim3(256), 0, s, nbox, need.p, view(),
                        ls.p, nleaf, kShiftLeaves, range.p, d_shift_count.p);
     n_shift_tasks = exclusive_scan_total(s, d_shift_count.p, d_shift_first.p, nbox, tmp);
+    {
+      std::vector<int> hc(nbox);
+      d_shift_count.download(hc.data(), nbox, s);
+      PBMP_HIP(hipStreamSynchronize(s));
+      shift_multi = std::any_of(hc.begin(), hc.end(), [](int c) { return c > 1; });
+    }
     d_shift_task.alloc(3 * (size_t)std::max(1, n_shift_tasks));
     hipLaunchKernelGGL(k_shift_fill, grid_for(nbox), dim3(256), 0, s, nbox, d_shift_first.p,
                        d_shift_count.p, range.p, kShiftLeaves, d_shift_task.p);

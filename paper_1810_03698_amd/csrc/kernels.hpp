@@ -140,6 +140,11 @@ void launch_xmy(hipStream_t s, int n, const double *b, const double *ax,
 void launch_precond(hipStream_t s, int N, const double *diag, double eps_ratio,
                     const double *u, double *z);
 // x += M^{-1} (V y) with nv basis vectors
+// z = M^{-1} u with the far-field strengths of z packed into src64/src32
+// (launch_precond followed by launch_pack_strengths, one launch)
+void launch_precond_pack(hipStream_t s, int N, int nf, const double *diag, double eps_ratio,
+                         const double *geo, const double *u, double *z, double *src64,
+                         float *src32);
 void launch_update_solution(hipStream_t s, int N, int nv, const double *V,
                             size_t ld, const double *y, const double *diag,
                             double eps_ratio, double *x);

@@ -599,14 +599,14 @@ void Runtime::build_site_lists() {
 }
 
 // -------------------------------------------------------------- operator
-void Runtime::apply(const double *x, double *y, bool f64) {
+void Runtime::apply(const double *x, double *y, bool f64, bool packed) {
   const int N = N_;
   const bool use64 = f64 || fp64();
   const double *val = (use64 && !fp64()) ? nval64_.p : nval_.p;
   // refinement products are FP64 by request: kept out of the kernel timers
   const bool timed = clock.on;
   if (f64 && !fp64()) clock.on = false;
-  launch_pack_strengths(s_, N, ru_.nf, geo_.p, x, src64_.p, src32_.p);
+  if (!packed) launch_pack_strengths(s_, N, ru_.nf, geo_.p, x, src64_.p, src32_.p);
   if (use_tree()) {
     tree_apply(*tree_, s_, use64, ru_.nf, N, geo_.p, src64_.p, src32_.p,
                tgt32_.p, o.kappa, part_.p, clock, floor_r2_);
@@ -658,7 +658,7 @@ void Runtime::krylov_reserve(int n) {
 
 int Runtime::gmres_core(int n, const KOp &op, const KPrec &prec, const KUpdate &update,
                         const double *b, double *x, double *V, double *w, double *z,
-                        double *ax, int *iters, bool *ax_valid) {
+                        double *ax, int *iters, bool *ax_valid, const KPrecOp &precop) {
   // ax_valid (may be null): in, ax already holds op(x) for this x (the last
   // residual product of the previous solve, x unchanged since), so the first
   // residual needs no product; out, whether ax holds op(x) on return
@@ -714,8 +714,12 @@ int Runtime::gmres_core(int n, const KOp &op, const KPrec &prec, const KUpdate &
     const double target = 0.5 * o.gmres_tol * bnorm;
     const int kmax = std::min(m, o.gmres_maxit - it);
     auto enqueue = [&](int k) {
-      prec(V + (size_t)k * ld, z);
-      op(z, w, false);
+      if (precop) {
+        precop(V + (size_t)k * ld, z, w);
+      } else {
+        prec(V + (size_t)k * ld, z);
+        op(z, w, false);
+      }
       // CGS2: h1 = V^T w, w -= V h1, h2 = V^T w, w -= V h2, |w|^2; the
       // totals land in hbuf (h1, h2, |w|^2) for the host
       int nb = launch_mdot_partial(s_, n, k + 1, V, ld, w, partial_.p);
@@ -811,7 +815,15 @@ int Runtime::gmres(const double *b, double *x, bool transpose, int *iters) {
   // the forward solve of the SCF loop reuses A x_ from the previous solve
   bool *valid = (!transpose && x == x_.p) ? &ax_holds_x_ : nullptr;
   if (!valid) ax_holds_x_ = false;  // ax_ is overwritten
-  return gmres_core(n, op, prec, update, b, x, V_.p, w_.p, z_.p, ax_.p, iters, valid);
+  // forward Arnoldi steps: preconditioner and strength packing in one launch
+  KPrecOp precop;
+  if (!transpose)
+    precop = [&](const double *v, double *zz, double *ww) {
+      launch_precond_pack(s_, N, ru_.nf, diag_.p, o.eps_in / o.eps_out, geo_.p, v, zz,
+                          src64_.p, src32_.p);
+      apply(zz, ww, false, true);
+    };
+  return gmres_core(n, op, prec, update, b, x, V_.p, w_.p, z_.p, ax_.p, iters, valid, precop);
 }
 
 // GMRES for a general operator of size n (right preconditioning, CGS2,
@@ -836,7 +848,8 @@ int Runtime::gmres_generic(int n, const KOp &op, const KPrec &prec, const double
     launch_axpy(s_, n, 1.0, gz_.p, x);
     sync();
   };
-  return gmres_core(n, op, prec, update, b, x, gV_.p, gw_.p, gz_.p, gax_.p, iters, ax_valid);
+  return gmres_core(n, op, prec, update, b, x, gV_.p, gw_.p, gz_.p, gax_.p, iters, ax_valid,
+                    KPrecOp());
 }
 
 // ------------------------------------------------------------- readout

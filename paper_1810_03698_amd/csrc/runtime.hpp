@@ -125,7 +125,8 @@ class Runtime {
   void alloc_work();
   // y = A x (internal order, device)
   // y = A x (transpose: A^T x); f64 forces the FP64 far field in mixed mode
-  void apply(const double *x, double *y, bool f64 = false);
+  // packed: the strengths of x are already in the source records
+  void apply(const double *x, double *y, bool f64 = false, bool packed = false);
   void apply_transpose(const double *x, double *y, bool f64 = false);
   void precond_T(const double *u, double *z);
   // GMRES on A x = b (device, internal order), x holds the initial guess.
@@ -156,11 +157,12 @@ class Runtime {
   using KOp = std::function<void(const double *, double *, bool)>;  // y = A x (f64 flag)
   using KPrec = std::function<void(const double *, double *)>;      // z = M^{-1} v
   using KUpdate = std::function<void(int, const double *)>;         // x += M^{-1} V y
+  using KPrecOp = std::function<void(const double *, double *, double *)>;  // z = M^{-1} v, w = A z
   int gmres_generic(int n, const KOp &op, const KPrec &prec, const double *b, double *x,
                     int *iters, bool *ax_valid = nullptr);
   int gmres_core(int n, const KOp &op, const KPrec &prec, const KUpdate &update,
                  const double *b, double *x, double *V, double *w, double *z, double *ax,
-                 int *iters, bool *ax_valid);
+                 int *iters, bool *ax_valid, const KPrecOp &precop);
   // ax_ = A x_ (gax_ = A sX_ for the layer system): the residual product of
   // the last solve, valid while neither x nor the operator changed
   bool ax_holds_x_ = false, gax_holds_x_ = false;

@@ -56,7 +56,7 @@ constexpr int kM2PChunkBoxes = PBMP_M2P_CHUNK;
 // about kP2PTaskWork / nt source panels (P2P) and kM2PTaskWork / nt boxes
 // (M2P, at most kM2PChunkBoxes), so that tasks take about the same time
 #ifndef PBMP_P2P_WORK
-#define PBMP_P2P_WORK 16384
+#define PBMP_P2P_WORK 12288
 #endif
 #ifndef PBMP_M2P_WORK
 #define PBMP_M2P_WORK 1024
@@ -126,6 +126,7 @@ class Tree {
   // shift tasks: the leaves under an accepted box with children in runs of
   // at most kShiftLeaves; task = (box, first leaf index, end leaf index)
   int n_shift_tasks = 0;
+  bool shift_multi = false;  // some box has several shift tasks
   Dbuf<int> d_shift_task, d_shift_first, d_shift_count;
   Dbuf<double> d_shift_part;  // [n_shift_tasks][2][ncoef]
   Dbuf<int> d_shift_toff, d_shift_tjq;  // per coefficient k: terms [toff[k], toff[k+1]), (j, k-j)
