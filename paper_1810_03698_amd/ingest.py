@@ -315,3 +315,26 @@ def load_tinker(xyz_path, param_path):
     """Site arrays for ``Solver.set_sites`` from a Tinker structure and
     parameter file (see ``tinker_sites``)."""
     return tinker_sites(read_tinker_xyz(xyz_path), read_tinker_params(param_path))
+
+
+def solve_files(vert_path, face_path, xyz_path, param_path, backward=False, **options):
+    """Solvation energy of a structure given as files (MSMS surface, Tinker
+    coordinates and parameters): returns the ``Solver.solve`` dict, plus the
+    gradients of ``Solver.backward`` when asked.  options go to ``Solver``
+    (the Thole factor defaults to the parameter file's when it has one)."""
+    from .pbmp import Solver
+    verts, tris, _, _ = read_msms(vert_path, face_path)
+    sites = load_tinker(xyz_path, param_path)
+    if "thole_a" not in options and len(sites["thole"]) == 1:
+        options["thole_a"] = sites["thole"][0]
+    s = Solver(**options)
+    try:
+        s.set_mesh(verts, tris)
+        s.set_sites(sites["xyz"], sites["q"], sites["d"], sites["Q9"], sites["alpha"],
+                    group=sites["group"])
+        out = s.solve()
+        if backward:
+            out["grad"] = s.backward(1.0)
+        return out
+    finally:
+        s.close()
