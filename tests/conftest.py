@@ -19,3 +19,13 @@ def gpu_lib():
     from paper_1810_03698_amd import pbmp
     lib = pbmp.load()
     return lib
+
+
+@pytest.fixture
+def say(capsys):
+    """Print a progress line past pytest's output capture, so that a long
+    test reports each finished step as it happens."""
+    def _say(*args):
+        with capsys.disabled():
+            print(*args, flush=True)
+    return _say

@@ -161,7 +161,7 @@ def test_fullsize_energy_properties(name):
         assert rel_t < (2e-5 if P <= 4 else 1e-5) + 1e-6
 
 
-def test_fullsize_gradients_fd_globule_5000():
+def test_fullsize_gradients_fd_globule_5000(say):
     """The 5000-atom globule (treecode, P = 5): adjoint gradients of the
     solvation energy for 4 seeded atoms against central differences
     (h = 1e-4 A) along a random direction per atom.  FP64 state: the base
@@ -171,27 +171,26 @@ def test_fullsize_gradients_fd_globule_5000():
     adjoint times the residual, and at 1e-12 it still moved these
     differences by ~5e-4 (1e-5 on the 1000-atom globule, where 1e-14 brings
     the agreement to 1e-8..1e-6).  The adjoint differentiates that FP64
-    state with mixed-precision transposed solves (precision switched after
-    the solve; their FP64 refinement holds the tolerance)."""
+    state with mixed-precision transposed solves at 1e-8 (precision switched
+    after the solve; their FP64 refinement holds the tolerance)."""
     w, m = _work("globule_5000")
     s = _solver(w, precision="fp64", gmres_restart=100, gmres_maxit=20000, scf_maxit=500,
                 warm_start=True)
     for gtol, stol in ((1e-6, 1e-6), (1e-9, 1e-8), (1e-12, 1e-11), (1e-14, 1e-12)):
         s.set_options(gmres_tol=gtol, scf_tol_debye=stol)
         base = s.solve(outputs=False)
-        print("base stage", gtol, base["dG"], base["status"], base["scf_iters"],
-              base["gmres_iters"], flush=True)
+        say("base stage", gtol, base["dG"], base["status"], base["scf_iters"],
+            base["gmres_iters"])
         assert base["status"] == 0
     # the adjoint's operator is the exact transpose of the solve's
     rng0 = np.random.default_rng(21)
     x, z = rng0.normal(size=2 * m.N), rng0.normal(size=2 * m.N)
     lhs, rhs = z @ s.matvec(x), s.matvec(z, transpose=True) @ x
-    print("transpose check", lhs, rhs, abs(lhs - rhs) / (np.linalg.norm(z) * np.linalg.norm(x)),
-          flush=True)
+    say("transpose check", lhs, rhs, abs(lhs - rhs) / (np.linalg.norm(z) * np.linalg.norm(x)))
     assert abs(lhs - rhs) < 1e-12 * np.linalg.norm(z) * np.linalg.norm(x)
-    s.set_options(precision="mixed", gmres_tol=1e-10)
+    s.set_options(precision="mixed", gmres_tol=1e-8)
     g = s.backward(1.0, verts=False)
-    print("backward", "status", g["status"], flush=True)
+    say("backward", "status", g["status"])
     assert g["status"] == 0
     s.set_options(precision="fp64", gmres_tol=1e-14, scf_tol_debye=1e-12)
     rng = np.random.default_rng(20)
@@ -214,6 +213,64 @@ def test_fullsize_gradients_fd_globule_5000():
         an = g["xyz"][l] @ u
         err = abs(an - fd) / max(abs(fd), 1e-2 * gmax)
         worst = max(worst, err)
-        print("atom", l, "adjoint", an, "fd", fd, "rel", err, flush=True)
+        say("atom", l, "adjoint", an, "fd", fd, "rel", err)
     s.close()
     assert worst < 1e-4
+
+
+def _traceless(rng, n):
+    A = rng.normal(size=(n, 3, 3))
+    A = A + A.transpose(0, 2, 1)
+    A -= np.trace(A, axis1=1, axis2=2)[:, None, None] * np.eye(3) / 3.0
+    return A.reshape(n, 9)
+
+
+def test_fullsize_multipole_gradients_fd_globule_5000(say):
+    """Gradients with respect to the charges, dipoles and quadrupoles of 20
+    seeded atoms of the 5000-atom globule (treecode, P = 5) against central
+    differences, one random direction per kind over all 20 atoms.  The
+    solvation energy is a homogeneous quadratic form in the permanent
+    multipoles (the right-hand side, the induced dipoles and the reaction
+    potentials are linear in them and the energy pairs two such quantities),
+    so a central difference is exact at any step: the step is large (0.5
+    along a unit direction) and only the solve tolerance limits the
+    agreement.  FP64 state at GMRES 1e-10 (its energy is within ~3e-6
+    kcal/mol of the 1e-14 one), differentiated by mixed transposed solves
+    at 1e-8 (the gradient's error follows the adjoint's, far below the
+    bar)."""
+    w, m = _work("globule_5000")
+    s = _solver(w, precision="fp64", gmres_restart=100, gmres_maxit=20000, scf_maxit=500,
+                warm_start=True)
+    for gtol, stol in ((1e-6, 1e-6), (1e-10, 1e-9)):
+        s.set_options(gmres_tol=gtol, scf_tol_debye=stol)
+        base = s.solve(outputs=False)
+        say("base stage", gtol, base["dG"], base["status"], base["scf_iters"],
+            base["gmres_iters"])
+        assert base["status"] == 0
+    s.set_options(precision="mixed", gmres_tol=1e-8)
+    g = s.backward(1.0, verts=False)
+    say("backward status", g["status"])
+    assert g["status"] == 0
+    s.set_options(precision="fp64", gmres_tol=1e-10, scf_tol_debye=1e-9)
+    rng = np.random.default_rng(22)
+    atoms = np.sort(rng.choice(len(w["q"]), 20, replace=False))
+    h = 0.5
+    for kind, width in (("q", 1), ("d", 3), ("Q9", 9)):
+        U = np.zeros((len(w["q"]), width))
+        U[atoms] = _traceless(rng, 20) if kind == "Q9" else rng.normal(size=(20, width))
+        U = U.reshape(w[kind].shape) / np.linalg.norm(U)
+        e = []
+        for sign in (1.0, -1.0):
+            mp_ = {k: w[k] for k in ("q", "d", "Q9")}
+            mp_[kind] = w[kind] + sign * h * U
+            s.set_sites(w["xyz"], mp_["q"], mp_["d"], mp_["Q9"], w["alpha"])
+            r = s.solve(outputs=False)
+            say(kind, sign, r["dG"], r["status"], r["scf_iters"], r["gmres_iters"])
+            assert r["status"] == 0
+            e.append(r["dG"])
+        fd = (e[0] - e[1]) / (2 * h)
+        an = float(np.sum(g[kind] * U))
+        rel = abs(an - fd) / abs(fd)
+        say(kind, "adjoint", an, "fd", fd, "rel", rel)
+        assert rel < 1e-4
+    s.close()
