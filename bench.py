@@ -28,12 +28,13 @@ COPY_BYTES = 256 << 20
 # passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean over the dispatches
 # of one solve) scaled by what the counters read for a 256 MiB copy
 # (FETCH_SIZE reads 0.5001 of the bytes read, WRITE_SIZE 1.0 of the bytes
-# written).  Keyed by (mode, kernel); valid only while the sources of the
-# kernel hash to the recorded value (otherwise traffic is reported null).
+# written).  Keyed by (mode, kernel); valid only for the workload and precision measured
+# and while the sources of the kernel hash to the recorded value (otherwise
+# traffic is reported null).
 TRAFFIC = {
-    ("treecode", "p2p"): {"fetch_kib": 5843.61, "fetch_scale": 0.50006,
+    ("treecode", "p2p"): {"workload": "sphere_81920", "precision": "mixed", "fetch_kib": 5843.61, "fetch_scale": 0.50006,
                           "write_kib": 51638.60, "write_scale": 1.0, "sha": "486e9fb11d200fa2"},
-    ("direct", "p2p"): {"fetch_kib": 20980.51, "fetch_scale": 0.50006,
+    ("direct", "p2p"): {"workload": "sphere_81920", "precision": "mixed", "fetch_kib": 20980.51, "fetch_scale": 0.50006,
                         "write_kib": 33280.0, "write_scale": 1.0, "sha": "614bbeac61608d8e"},
 }
 TRAFFIC_SOURCES = {
@@ -52,9 +53,11 @@ def _sources_hash(files):
     return h.hexdigest()[:16]
 
 
-def traffic_bytes(mode, kernel):
+def traffic_bytes(mode, kernel, workload, precision):
     rec = TRAFFIC.get((mode, kernel))
-    if rec is None or rec["sha"] != _sources_hash(TRAFFIC_SOURCES[(mode, kernel)]):
+    if rec is None or rec["workload"] != workload or rec["precision"] != precision:
+        return None
+    if rec["sha"] != _sources_hash(TRAFFIC_SOURCES[(mode, kernel)]):
         return None
     return rec["fetch_kib"] * 1024 / rec["fetch_scale"] + rec["write_kib"] * 1024 / rec["write_scale"]
 ALG_FLOP_PER_PAIR = 33  # four kernels per (target, far-field node) pair
@@ -63,18 +66,26 @@ PEAK_FP32_NONPACKED = 78.6  # 256 CU x 64 lanes x 2 FLOP x 2.4 GHz
 
 
 def _m2p_flops(order):
-    """FLOP per (target, box) pair of the implemented M2P evaluation: per
-    coefficient k != 0 of the Laplace/Yukawa recurrences 6 n1 + 3 n2 + 13
-    (n1, n2 = number of k_i >= 1, >= 2), 8 for the four moment dot products
-    per coefficient, and 14 for the pair set-up (FMA = 2)."""
+    """FLOP per (target, box) pair of the implemented M2P evaluation, not
+    counting products with 1, terms with 0 or additions to 0.  Per
+    coefficient k != 0 of the Laplace/Yukawa recurrences (n1, n2 = number of
+    k_i >= 1, >= 2): 6 n1 - 3 for the three sums over the first-lower
+    coefficients, 3 (n2 - 1) for the three over the second-lower ones, and 5
+    (|k| = 1), 7 (no k_i >= 2) or 13 to combine them; 8 per coefficient for
+    the four moment dot products; 14 for the pair set-up.  P = 4: 955,
+    P = 5: 1630."""
     total = 14
     for s in range(order + 1):
         for i in range(s, -1, -1):
             for j in range(s - i, -1, -1):
                 k = (i, j, s - i - j)
                 total += 8
-                if s:
-                    total += 6 * sum(e >= 1 for e in k) + 3 * sum(e >= 2 for e in k) + 13
+                if not s:
+                    continue
+                n1 = sum(e >= 1 for e in k)
+                n2 = sum(e >= 2 for e in k)
+                total += 6 * n1 - 3 + (3 * (n2 - 1) if n2 else 0)
+                total += 5 if s == 1 else (7 if n2 == 0 else 13)
     return total
 
 
@@ -230,7 +241,7 @@ def main():
     achieved = per_launch / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
-                "traffic": traffic_bytes(mode, name), "traffic_unit": "bytes per launch",
+                "traffic": traffic_bytes(mode, name, args.workload, args.precision), "traffic_unit": "bytes per launch",
                 "kernel": name, "avg_launch_ms": avg_ms,
                 "frac_of_nonpacked_fp32": achieved / PEAK_FP32_NONPACKED,
                 "p2p_ms_total": st["p2p_ms"], "m2p_ms_total": st["m2p_ms"],

@@ -123,54 +123,95 @@ __device__ inline void node_kernels(T X, T Y, T Z, T nx, T ny, T nz, T nR,
   }
 }
 
+// Far-field readout: one site per lane (64 sites per block), the panels of
+// one source chunk staged through LDS in tiles of kRoTile records (coalesced
+// 16-byte loads of the contiguous records, all issued before the first
+// store), per-chunk partial sums part[chunk][site][k].  Per panel the sums
+// are formed as in the operator: node differences from FP64 positions, the
+// kernels in T, the panel's strengths applied before the FP64 accumulation.
+constexpr int kRoTile = 64;
+
 template <bool FP64, bool FULL>
-__global__ __launch_bounds__(256) void k_readout_far(
+__global__ __launch_bounds__(64) void k_readout_far(
     int N, int M, int nf, const double *__restrict__ src64,
     const float *__restrict__ src32, const double *__restrict__ xyz, int chunk,
     double *__restrict__ part) {
   constexpr int NO = FULL ? 10 : 4;
-  __shared__ double red[256];
-  const int l = blockIdx.x;
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  __shared__ __align__(16) double s64[kRoTile * 16];
+  __shared__ __align__(16) float s32[FP64 ? 4 : kRoTile * 16];
+  const int lane = (int)threadIdx.x;
+  const int l = blockIdx.x * 64 + lane;
+  const int lc = min(l, M - 1);
   const int j0 = blockIdx.y * chunk, j1 = min(N, j0 + chunk);
-  const double P[3] = {xyz[3 * l], xyz[3 * l + 1], xyz[3 * l + 2]};
+  const double P[3] = {xyz[3 * lc], xyz[3 * lc + 1], xyz[3 * lc + 2]};
   double acc[NO];
   for (int k = 0; k < NO; ++k) acc[k] = 0.0;
-  for (int j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
-    if (FP64) {
-      const double *r = src64 + 16 * (size_t)j;
-      double g[NO], h[NO];
-      for (int k = 0; k < NO; ++k) g[k] = h[k] = 0.0;
-      const double nR = r[9] * P[0] + r[10] * P[1] + r[11] * P[2] - r[12];
-      for (int qn = 0; qn < nf; ++qn)
-        node_kernels<double, FULL>(P[0] - r[3 * qn], P[1] - r[3 * qn + 1],
-                                   P[2] - r[3 * qn + 2], r[9], r[10], r[11],
-                                   nR, g, h);
-      for (int k = 0; k < NO; ++k) acc[k] += r[13] * g[k] - r[14] * h[k];
-    } else {
-      const float *r = src32 + 16 * (size_t)j;
-      const double *r64 = src64 + 16 * (size_t)j;
-      float g[NO], h[NO];
-      for (int k = 0; k < NO; ++k) g[k] = h[k] = 0.0f;
-      const float nR = (float)(r64[9] * P[0] + r64[10] * P[1] + r64[11] * P[2] - r64[12]);
-      for (int qn = 0; qn < nf; ++qn)
-        node_kernels<float, FULL>((float)(P[0] - r64[3 * qn]),
-                                  (float)(P[1] - r64[3 * qn + 1]),
-                                  (float)(P[2] - r64[3 * qn + 2]), r[9], r[10],
-                                  r[11], nR, g, h);
-      for (int k = 0; k < NO; ++k)
-        acc[k] += (double)(r[13] * g[k] - r[14] * h[k]);
+  for (int jt = j0; jt < j1; jt += kRoTile) {
+    const int nj = min(kRoTile, j1 - jt);
+    __syncthreads();
+    {
+      const d2 *g = reinterpret_cast<const d2 *>(src64 + 16 * (size_t)jt);
+      d2 *d = reinterpret_cast<d2 *>(s64);
+      const int n = nj * 8;
+      d2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = lane + 64 * u;
+        if (e < n) v[u] = g[e];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = lane + 64 * u;
+        if (e < n) d[e] = v[u];
+      }
+      if constexpr (!FP64) {
+        const f4 *g32 = reinterpret_cast<const f4 *>(src32 + 16 * (size_t)jt);
+        f4 *d32 = reinterpret_cast<f4 *>(s32);
+        const int n32 = nj * 4;
+        f4 w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = lane + 64 * u;
+          if (e < n32) w[u] = g32[e];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = lane + 64 * u;
+          if (e < n32) d32[e] = w[u];
+        }
+      }
+    }
+    __syncthreads();
+    for (int jj = 0; jj < nj; ++jj) {
+      const double *r64 = s64 + 16 * jj;
+      if constexpr (FP64) {
+        double g[NO], h[NO];
+        for (int k = 0; k < NO; ++k) g[k] = h[k] = 0.0;
+        const double nR = r64[9] * P[0] + r64[10] * P[1] + r64[11] * P[2] - r64[12];
+        for (int qn = 0; qn < nf; ++qn)
+          node_kernels<double, FULL>(P[0] - r64[3 * qn], P[1] - r64[3 * qn + 1],
+                                     P[2] - r64[3 * qn + 2], r64[9], r64[10], r64[11],
+                                     nR, g, h);
+        for (int k = 0; k < NO; ++k) acc[k] += r64[13] * g[k] - r64[14] * h[k];
+      } else {
+        const float *r = s32 + 16 * jj;
+        float g[NO], h[NO];
+        for (int k = 0; k < NO; ++k) g[k] = h[k] = 0.0f;
+        const float nR = (float)(r64[9] * P[0] + r64[10] * P[1] + r64[11] * P[2] - r64[12]);
+        for (int qn = 0; qn < nf; ++qn)
+          node_kernels<float, FULL>((float)(P[0] - r64[3 * qn]),
+                                    (float)(P[1] - r64[3 * qn + 1]),
+                                    (float)(P[2] - r64[3 * qn + 2]), r[9], r[10],
+                                    r[11], nR, g, h);
+        for (int k = 0; k < NO; ++k)
+          acc[k] += (double)(r[13] * g[k] - r[14] * h[k]);
+      }
     }
   }
-  for (int k = 0; k < NO; ++k) {
-    red[threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) part[((size_t)blockIdx.y * M + l) * NO + k] = red[0];
-    __syncthreads();
-  }
+  if (l < M)
+    for (int k = 0; k < NO; ++k) part[((size_t)blockIdx.y * M + l) * NO + k] = acc[k];
 }
 
 // Near-singular correction at the sites (19-node rule instead of the far
@@ -440,6 +481,12 @@ void launch_rhs(hipStream_t s, bool fp64, int N, int M, const double *geo,
   PBMP_HIP(hipGetLastError());
 }
 
+int readout_chunks(int N, int M) {
+  const int tiles = (std::max(M, 1) + 63) / 64;
+  const int c = std::min(256, (4096 + tiles - 1) / tiles);
+  return std::max(1, std::min(c, N / 64));
+}
+
 void launch_readout(hipStream_t s, bool fp64, bool full, int N, int M,
                     const double *src64, const float *src32, const double *geo,
                     const double *verts, const int *tri, const RuleArgs &ru,
@@ -447,9 +494,9 @@ void launch_readout(hipStream_t s, bool fp64, bool full, int N, int M,
                     const int *scol, int nchunk, double *part, double *out) {
   if (M <= 0) return;
   const int chunk = (N + nchunk - 1) / nchunk;
-  dim3 grid(M, nchunk);
-#define PBMP_RO(F64, FULL)                                                    \
-  hipLaunchKernelGGL((k_readout_far<F64, FULL>), grid, dim3(256), 0, s, N, M, \
+  dim3 grid((M + 63) / 64, nchunk);
+#define PBMP_RO(F64, FULL)                                                   \
+  hipLaunchKernelGGL((k_readout_far<F64, FULL>), grid, dim3(64), 0, s, N, M, \
                      ru.nf, src64, src32, xyz, chunk, part)
   if (fp64 && full) PBMP_RO(true, true);
   else if (fp64) PBMP_RO(true, false);

@@ -77,6 +77,9 @@ void launch_readout(hipStream_t s, bool fp64, bool full, int N, int M,
                     const double *verts, const int *tri, const RuleArgs &ru,
                     const double *x, const double *xyz, const int *srow,
                     const int *scol, int nchunk, double *part, double *out);
+// Source chunks of the far readout for N panels and M sites (enough blocks
+// of 64 sites x one chunk to fill the device); part holds nchunk * M * 10.
+int readout_chunks(int N, int M);
 
 // Coulomb field of the permanent multipoles at the sites, excluding pairs of
 // the same polarisation group: Eperm[3M] = -grad phi_perm / eps_in.

@@ -545,8 +545,7 @@ void Runtime::set_sites(int64_t m, const double *xyz, const double *q,
   f_.alloc(N_);
   dmu2_.alloc(1);
   e_.alloc(10);
-  ro_chunks_ = std::max(1, std::min(64, (2048 + M - 1) / M));
-  ro_chunks_ = std::min(ro_chunks_, std::max(1, N_ / 256));
+  ro_chunks_ = readout_chunks(N_, M);
   rpart_.alloc((size_t)ro_chunks_ * M * 10);
   solved_ = false;
 }

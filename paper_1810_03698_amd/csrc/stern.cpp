@@ -32,8 +32,7 @@ void Runtime::set_probe(int M, const std::vector<double> &pts) {
   pxyz_.upload(pts.data(), pts.size(), s_);
   prow_.upload(row.data(), row.size(), s_);
   pcol_.upload(col.data(), col.size(), s_);
-  p_chunks_ = std::max(1, std::min(64, (2048 + M - 1) / M));
-  p_chunks_ = std::min(p_chunks_, std::max(1, N_ / 256));
+  p_chunks_ = readout_chunks(N_, M);
   ppart_.alloc((size_t)p_chunks_ * M * 10);
   pout_.alloc(4 * (size_t)M);
   sync();
