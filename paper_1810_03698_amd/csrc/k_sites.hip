@@ -274,18 +274,26 @@ __global__ __launch_bounds__(64) void k_readout_near(
 }
 
 // ------------------------------------------------------------- Coulomb
-__global__ void k_perm_field(int M, const double *__restrict__ xyz,
-                             const double *__restrict__ q,
-                             const double *__restrict__ d,
-                             const double *__restrict__ Q9,
-                             const int *__restrict__ group, double inv_eps,
-                             double *__restrict__ E) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= M) return;
+// Sum over the 64 lanes of a wave (every lane receives the total).
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// The site-pair kernels below take one wave per site l, lanes over the
+// sources m (strided), and reduce over the wave at the end.
+__global__ __launch_bounds__(64) void k_perm_field(int M, const double *__restrict__ xyz,
+                                                   const double *__restrict__ q,
+                                                   const double *__restrict__ d,
+                                                   const double *__restrict__ Q9,
+                                                   const int *__restrict__ group,
+                                                   double inv_eps, double *__restrict__ E) {
+  const int l = blockIdx.x;
+  const int lane = (int)threadIdx.x;
   const double P[3] = {xyz[3 * l], xyz[3 * l + 1], xyz[3 * l + 2]};
   const int gl = group[l];
   double g[3] = {0.0, 0.0, 0.0};
-  for (int m = 0; m < M; ++m) {
+  for (int m = lane; m < M; m += 64) {
     if (group[m] == gl) continue;  // includes m == l
     const double R[3] = {P[0] - xyz[3 * m], P[1] - xyz[3 * m + 1],
                          P[2] - xyz[3 * m + 2]};
@@ -303,21 +311,23 @@ __global__ void k_perm_field(int M, const double *__restrict__ xyz,
       g[a] += -q[m] * R[a] * ri3 + pm[a] * ri3 - 3.0 * pR * R[a] * ri5 +
               QR[a] * ri5 - 2.5 * S * R[a] * ri7;
   }
-  for (int a = 0; a < 3; ++a) E[3 * l + a] = -g[a] * inv_eps;
+  for (int a = 0; a < 3; ++a) g[a] = wave_sum(g[a]);
+  if (lane == 0)
+    for (int a = 0; a < 3; ++a) E[3 * l + a] = -g[a] * inv_eps;
 }
 
 template <bool FULL>
-__global__ void k_induced(int M, const double *__restrict__ xyz,
-                          const double *__restrict__ mu,
-                          const double *__restrict__ alpha, double ta,
-                          double inv_eps, double *__restrict__ out) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= M) return;
+__global__ __launch_bounds__(64) void k_induced(int M, const double *__restrict__ xyz,
+                                                const double *__restrict__ mu,
+                                                const double *__restrict__ alpha, double ta,
+                                                double inv_eps, double *__restrict__ out) {
+  const int l = blockIdx.x;
+  const int lane = (int)threadIdx.x;
   const double P[3] = {xyz[3 * l], xyz[3 * l + 1], xyz[3 * l + 2]};
   const double al = alpha[l];
   double acc[10];
   for (int k = 0; k < 10; ++k) acc[k] = 0.0;
-  for (int m = 0; m < M; ++m) {
+  for (int m = lane; m < M; m += 64) {
     if (m == l) continue;
     const double R[3] = {P[0] - xyz[3 * m], P[1] - xyz[3 * m + 1],
                          P[2] - xyz[3 * m + 2]};
@@ -349,9 +359,13 @@ __global__ void k_induced(int M, const double *__restrict__ xyz,
     }
   }
   if (FULL) {
-    for (int k = 0; k < 10; ++k) out[10 * l + k] = acc[k] * inv_eps;
+    for (int k = 0; k < 10; ++k) acc[k] = wave_sum(acc[k]);
+    if (lane == 0)
+      for (int k = 0; k < 10; ++k) out[10 * l + k] = acc[k] * inv_eps;
   } else {
-    for (int a = 0; a < 3; ++a) out[3 * l + a] = -acc[1 + a] * inv_eps;
+    for (int a = 0; a < 3; ++a) acc[1 + a] = wave_sum(acc[1 + a]);
+    if (lane == 0)
+      for (int a = 0; a < 3; ++a) out[3 * l + a] = -acc[1 + a] * inv_eps;
   }
 }
 
@@ -517,7 +531,7 @@ void launch_perm_field(hipStream_t s, int M, const double *xyz,
                        const double *q, const double *d, const double *Q9,
                        const int *group, double eps_in, double *E) {
   if (M <= 0) return;
-  hipLaunchKernelGGL(k_perm_field, dim3((M + 127) / 128), dim3(128), 0, s, M,
+  hipLaunchKernelGGL(k_perm_field, dim3(M), dim3(64), 0, s, M,
                      xyz, q, d, Q9, group, 1.0 / eps_in, E);
   PBMP_HIP(hipGetLastError());
 }
@@ -527,10 +541,10 @@ void launch_induced(hipStream_t s, bool full, int M, const double *xyz,
                     double eps_in, double *out) {
   if (M <= 0) return;
   if (full)
-    hipLaunchKernelGGL(k_induced<true>, dim3((M + 127) / 128), dim3(128), 0, s,
+    hipLaunchKernelGGL(k_induced<true>, dim3(M), dim3(64), 0, s,
                        M, xyz, mu, alpha, thole_a, 1.0 / eps_in, out);
   else
-    hipLaunchKernelGGL(k_induced<false>, dim3((M + 127) / 128), dim3(128), 0, s,
+    hipLaunchKernelGGL(k_induced<false>, dim3(M), dim3(64), 0, s,
                        M, xyz, mu, alpha, thole_a, 1.0 / eps_in, out);
   PBMP_HIP(hipGetLastError());
 }
