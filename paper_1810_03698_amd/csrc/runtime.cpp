@@ -682,9 +682,13 @@ int Runtime::gmres_core(int n, const KOp &op, const KPrec &prec, const KUpdate &
     return 0;
   }
   // Mixed precision: restart residuals come from the FP32-far-field product
-  // while they keep falling; once a cycle stalls (the residual floor of that
-  // product), they are recomputed with the FP64 product, which turns the
-  // restarts into iterative refinement with FP64 residuals.
+  // while they keep falling; once one reaches that product's accuracy (a
+  // relative residual of kFloor32) or a cycle stalls, they are recomputed
+  // with the FP64 product, which turns the restarts into iterative
+  // refinement with FP64 residuals.  Before that, a cycle aims no lower
+  // than kFloor32: Arnoldi steps beyond it would only solve the FP32
+  // system more exactly.
+  constexpr double kFloor32 = 1e-6;
   bool refine = false;
   double prev = 0.0;
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
@@ -695,7 +699,8 @@ int Runtime::gmres_core(int n, const KOp &op, const KPrec &prec, const KUpdate &
     have_ax = false;
     launch_xmy(s_, n, b, ax, w);
     double beta = std::sqrt(dot_host(w, w));
-    if (!refine && !fp64() && it > 0 && beta / bnorm > 0.5 * prev && beta / bnorm > o.gmres_tol) {
+    if (!refine && !fp64() && beta / bnorm > o.gmres_tol &&
+        ((it > 0 && beta / bnorm > 0.5 * prev) || beta / bnorm <= kFloor32)) {
       refine = true;
       op(x, ax, true);
       launch_xmy(s_, n, b, ax, w);
@@ -710,7 +715,12 @@ int Runtime::gmres_core(int n, const KOp &op, const KPrec &prec, const KUpdate &
     launch_scale(s_, n, 1.0 / beta, w, V);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
-    const double target = 0.5 * o.gmres_tol * bnorm;
+    // a refinement cycle (FP32 Arnoldi on an FP64 residual) gains at most
+    // about kFloor32 per restart, so it aims no lower than that either
+    const double target =
+        fp64() ? 0.5 * bnorm * o.gmres_tol
+        : refine ? std::max(0.5 * bnorm * o.gmres_tol, kFloor32 * beta)
+                 : 0.5 * bnorm * std::max(o.gmres_tol, kFloor32);
     const int kmax = std::min(m, o.gmres_maxit - it);
     auto enqueue = [&](int k) {
       if (precop) {
