@@ -71,7 +71,10 @@ extern "C" {
 #define PBMP_FP64 0
 #define PBMP_MIXED 1 /* FP32 far field (P2P, M2P, far readout, RHS pair
                         terms) with FP64 accumulation; FP64 near/self
-                        integrals, Krylov vectors, SCF and energy */
+                        integrals, Krylov vectors, SCF and energy.  GMRES
+                        tolerances below 1e-6 are met by iterative
+                        refinement: restart residuals from the FP64
+                        operator, Arnoldi steps on the FP32 one */
 
 typedef struct pbmp_options {
   double eps_in;        /* solute dielectric constant (eq. pde), > 0        */
