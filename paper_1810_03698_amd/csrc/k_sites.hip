@@ -257,18 +257,18 @@ __global__ __launch_bounds__(64) void k_readout_near(
       }
     }
   }
+  // the far chunks' partial sums join the lanes' near sums (chunk c on lane
+  // c mod 64), then a fixed-order tree over the lanes
   for (int k = 0; k < NO; ++k) {
-    red[threadIdx.x] = acc[k];
+    double v = acc[k];
+    for (int c = threadIdx.x; c < nchunk; c += blockDim.x) v += part[((size_t)c * M + l) * NO + k];
+    red[threadIdx.x] = v;
     __syncthreads();
     for (int w = 32; w > 0; w >>= 1) {
       if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
       __syncthreads();
     }
-    if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int c = 0; c < nchunk; ++c) s += part[((size_t)c * M + l) * NO + k];
-      out[(size_t)l * NO + k] = kFourPi * (s + red[0]);
-    }
+    if (threadIdx.x == 0) out[(size_t)l * NO + k] = kFourPi * red[0];
     __syncthreads();
   }
 }
@@ -496,9 +496,10 @@ void launch_rhs(hipStream_t s, bool fp64, int N, int M, const double *geo,
 }
 
 int readout_chunks(int N, int M) {
+  // about 4096 blocks, each chunk at least one tile of panels
   const int tiles = (std::max(M, 1) + 63) / 64;
-  const int c = std::min(256, (4096 + tiles - 1) / tiles);
-  return std::max(1, std::min(c, N / 64));
+  const int c = (4096 + tiles - 1) / tiles;
+  return std::max(1, std::min(c, N / kRoTile));
 }
 
 void launch_readout(hipStream_t s, bool fp64, bool full, int N, int M,
