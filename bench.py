@@ -62,7 +62,7 @@ def traffic_bytes(mode, kernel, workload, precision):
     return rec["fetch_kib"] * 1024 / rec["fetch_scale"] + rec["write_kib"] * 1024 / rec["write_scale"]
 ALG_FLOP_PER_PAIR = 33  # four kernels per (target, far-field node) pair
 PEAK_FP32_VECTOR = 157.3  # TFLOP/s, MI355X published (packed FP32)
-PEAK_FP32_NONPACKED = 78.6  # 256 CU x 64 lanes x 2 FLOP x 2.4 GHz
+PEAK_FP32_NONPACKED = 78.6  # nominal: 256 CU x 64 lanes x 2 FLOP x 2.4 GHz
 
 
 def _m2p_flops(order):
@@ -172,7 +172,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU "
               "path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))

@@ -179,7 +179,11 @@ def _sphere_eigs(n, R, kappa):
             kappa ** 2 * R ** 2 * i_n * kp_n + 0.5)
 
 
-def test_sphere_eigenvalues_survey_values():
+def test_sphere_eigenvalues_tabulated():
+    """Eigenvalues of V_L, K_L, V_Y, K_Y on the sphere R = 4 A, kappa = 0.125
+    for degrees 0-2, tabulated to 7 digits: R/(2n+1), -1/(2(2n+1)) and the
+    modified-spherical-Bessel products of the Yukawa single and double
+    layers."""
     ref = {0: (4, -0.5, 2.5284822, -0.4481808),
            1: (4 / 3, -1 / 6, 1.2436599, -0.1736491),
            2: (0.8, -0.1, 0.7820869, -0.1020011)}
