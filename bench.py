@@ -63,6 +63,7 @@ def traffic_bytes(mode, kernel, workload, precision):
 ALG_FLOP_PER_PAIR = 33  # four kernels per (target, far-field node) pair
 PEAK_FP32_VECTOR = 157.3  # TFLOP/s, MI355X published (packed FP32)
 PEAK_FP32_NONPACKED = 78.6  # nominal: 256 CU x 64 lanes x 2 FLOP x 2.4 GHz
+PEAK_FP64_VECTOR = 78.6  # TFLOP/s, MI355X published
 
 
 def _m2p_flops(order):
@@ -239,11 +240,14 @@ def main():
         name, avg_ms = "m2p", m2p_avg
         per_launch = _m2p_flops(int(p.get("order_P", 4))) * st["m2p_pairs"] / max(1, st["m2p_launches"])
     achieved = per_launch / (avg_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
+    # the far field runs in FP32 in mixed precision and in FP64 otherwise
+    peak = PEAK_FP32_VECTOR if args.precision == "mixed" else PEAK_FP64_VECTOR
+    roofline = {"bound": "alu", "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": traffic_bytes(mode, name, args.workload, args.precision), "traffic_unit": "bytes per launch",
                 "kernel": name, "avg_launch_ms": avg_ms,
-                "frac_of_nonpacked_fp32": achieved / PEAK_FP32_NONPACKED,
+                "frac_of_nonpacked_fp32": (achieved / PEAK_FP32_NONPACKED
+                                           if args.precision == "mixed" else None),
                 "p2p_ms_total": st["p2p_ms"], "m2p_ms_total": st["m2p_ms"],
                 "p2m_ms_total": st["p2m_ms"],
                 "p2p_avg_ms": p2p_avg, "m2p_avg_ms": m2p_avg,
