@@ -115,6 +115,18 @@ class Mesh:
                                   ctypes.c_int(i1), _p(phi), _p(dphi), _p(out))
         return out
 
+    def near_correction_sums(self, phi, dphi, rows=None):
+        """[n,4] near-field corrections (method's entry minus far-rule entry
+        over the singular and near-singular pairs) applied to the densities,
+        in the order (V_L dphi, K_L phi, V_Y dphi, K_Y phi), rows i0:i1."""
+        i0, i1 = (0, self.N) if rows is None else rows
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        dphi = np.ascontiguousarray(dphi, dtype=np.float64)
+        out = np.empty((i1 - i0, 4))
+        _load().orc_near_correction_sums(ctypes.byref(self.c), ctypes.c_int(i0),
+                                         ctypes.c_int(i1), _p(phi), _p(dphi), _p(out))
+        return out
+
     def self_integrals(self, j, point=None):
         c = self.cen[j] if point is None else np.asarray(point, dtype=np.float64)
         c = np.ascontiguousarray(c)

@@ -231,3 +231,36 @@ void orc_self_integrals(const orc_mesh *m, int j, const double *c, double *out)
 {
     self_integrals(m, j, c, &out[0], &out[1]);
 }
+
+/* Near-field corrections for targets [i0, i1): for every pair that the
+ * method integrates with a rule other than the far rule (the singular pair
+ * j == i and the near-singular pairs |c_i - c_j| < eta sqrt(A_i)), the
+ * method's entry minus the far-rule entry, applied to the densities:
+ *   out_i = sum_{j near or self} (E_ij - F_ij) * (dphi_j, phi_j, dphi_j, phi_j).
+ * A treecode product is its far-rule sum (expansions for accepted boxes,
+ * far rule elsewhere) plus these corrections. */
+void orc_near_correction_sums(const orc_mesh *m, int i0, int i1, const double *phi,
+                              const double *dphi, double *out /* [(i1-i0)*4] */)
+{
+    int N = m->N;
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int i = i0; i < i1; ++i) {
+        const double *ci = m->cen + 3 * (size_t)i;
+        double s[4] = {0, 0, 0, 0};
+        for (int j = 0; j < N; ++j) {
+            const double *cj = m->cen + 3 * (size_t)j;
+            double d[3] = {ci[0] - cj[0], ci[1] - cj[1], ci[2] - cj[2]};
+            double dist = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (j != i && !(dist < m->eta * sqrt(m->area[i])))
+                continue;
+            double e[4], f[4];
+            entry(m, i, j, e);
+            rule_entries(m, j, ci, m->nf, m->fb, m->fw, f);
+            s[0] += (e[0] - f[0]) * dphi[j];
+            s[1] += (e[1] - f[1]) * phi[j];
+            s[2] += (e[2] - f[2]) * dphi[j];
+            s[3] += (e[3] - f[3]) * phi[j];
+        }
+        for (int k = 0; k < 4; ++k) out[4 * (size_t)(i - i0) + k] = s[k];
+    }
+}

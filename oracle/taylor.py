@@ -139,3 +139,102 @@ def moments(points, normals, sv, sk, yc, P):
             acc += k[a] * normals[:, a] * h[:, 0] ** km[0] * h[:, 1] ** km[1] * h[:, 2] ** km[2]
         mk[n] = np.sum(sk * acc)
     return m, mk
+
+
+# ------------------------------------------------------------------ batches
+# The same truncated power series for many expansion points at once:
+# coefficient arrays of shape [ncoef, n], one column per (target, centre)
+# pair.  Used by the oracle's treecode product, where the scalar Jet would
+# be too slow; pinned against the scalar functions above.
+
+def _product_table(P):
+    """For every coefficient n of a product: the index pairs (n1, n2) of
+    the factors' coefficients whose multi-indices add up to it."""
+    ks = multi_indices(P)
+    index = {k: n for n, k in enumerate(ks)}
+    terms = [([], []) for _ in ks]
+    for n1, k1 in enumerate(ks):
+        for n2, k2 in enumerate(ks):
+            s = (k1[0] + k2[0], k1[1] + k2[1], k1[2] + k2[2])
+            if sum(s) <= P:
+                terms[index[s]][0].append(n1)
+                terms[index[s]][1].append(n2)
+    return [(np.array(a), np.array(b)) for a, b in terms]
+
+
+class BatchJet:
+    """Truncated series in three variables for n expansion points."""
+
+    _tables = {}
+
+    def __init__(self, P, c):
+        self.P = P
+        self.c = c
+        if P not in BatchJet._tables:
+            BatchJet._tables[P] = _product_table(P)
+
+    def __mul__(self, o):
+        if not isinstance(o, BatchJet):
+            return BatchJet(self.P, self.c * o)
+        out = np.empty_like(self.c)
+        for n, (a, b) in enumerate(BatchJet._tables[self.P]):
+            out[n] = np.einsum("ij,ij->j", self.c[a], o.c[b])
+        return BatchJet(self.P, out)
+
+    __rmul__ = __mul__
+
+    def __add__(self, o):
+        return BatchJet(self.P, self.c + o.c)
+
+    def _unit(self):
+        u = np.zeros_like(self.c)
+        u[0] = 1.0
+        return BatchJet(self.P, u)
+
+    def power(self, alpha):
+        c0 = self.c[0].copy()
+        t = BatchJet(self.P, self.c / c0)
+        t.c[0] = 0.0
+        out, term, coef = self._unit(), self._unit(), 1.0
+        for n in range(1, self.P + 1):
+            coef *= (alpha - n + 1) / n
+            term = term * t
+            out = out + term * coef
+        return out * (c0 ** alpha)
+
+    def exp(self):
+        c0 = self.c[0].copy()
+        t = BatchJet(self.P, self.c.copy())
+        t.c[0] = 0.0
+        out, term = self._unit(), self._unit()
+        for n in range(1, self.P + 1):
+            term = term * t * (1.0 / n)
+            out = out + term
+        return out * np.exp(c0)
+
+
+def _u_batch(D, P):
+    """u(h) = |D - h|^2 for D [n, 3] as a batch of series."""
+    ks = multi_indices(P)
+    index = {k: n for n, k in enumerate(ks)}
+    c = np.zeros((len(ks), len(D)))
+    c[0] = np.einsum("ij,ij->i", D, D)
+    for a in range(3):
+        e = [0, 0, 0]
+        e[a] = 1
+        c[index[tuple(e)]] = -2.0 * D[:, a]
+        if P >= 2:
+            e[a] = 2
+            c[index[tuple(e)]] = 1.0
+    return BatchJet(P, c)
+
+
+def laplace_coefficients_batch(D, P):
+    """Coefficients [ncoef, n] of 1/|D - h| for D = x - y_c [n, 3]."""
+    return _u_batch(np.asarray(D, float), P).power(-0.5).c
+
+
+def yukawa_coefficients_batch(D, P, kappa):
+    """Coefficients [ncoef, n] of exp(-kappa |D - h|)/|D - h|."""
+    u = _u_batch(np.asarray(D, float), P)
+    return ((u.power(0.5) * (-kappa)).exp() * u.power(-0.5)).c

@@ -19,11 +19,20 @@ class SolvationEnergy(torch.autograd.Function):
                          alpha.detach().contiguous())
         r = solver.solve(outputs=False)
         ctx.solver = solver
+        ctx.state_id = solver.state_id
         ctx.device = xyz.device
         return torch.tensor(r["dG"], dtype=torch.float64, device=xyz.device)
 
     @staticmethod
     def backward(ctx, grad_out):
+        if ctx.solver.state_id != ctx.state_id:
+            # the library differentiates the solver's current state: a later
+            # set_mesh / set_sites / solve on the same solver replaced the
+            # state this energy came from
+            raise RuntimeError(
+                "solvation_energy: the Solver was used again after this energy was "
+                "computed (its mesh, sites or solution changed); use one Solver per "
+                "energy that is differentiated")
         need_v = ctx.needs_input_grad[1]
         dev = ctx.device if ctx.device.type == "cuda" else None
         g = ctx.solver.backward(float(grad_out), verts=need_v, device=dev)

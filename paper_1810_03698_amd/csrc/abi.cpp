@@ -1,6 +1,7 @@
 // C-ABI entry points (include/pbmp.h).  Every call converts library errors
 // into status codes and a per-context message.
 #include <cstring>
+#include <memory>
 
 #include "runtime.hpp"
 
@@ -57,9 +58,10 @@ int pbmp_create(const pbmp_options *o, pbmp_ctx **out) {
   if (!o || !out) return PBMP_EARG;
   *out = nullptr;
   try {
-    auto *c = new pbmp_ctx();
+    // the context is released if the runtime's constructor throws
+    std::unique_ptr<pbmp_ctx> c(new pbmp_ctx());
     c->rt.reset(new pbmp::Runtime(*o));
-    *out = c;
+    *out = c.release();
     return PBMP_OK;
   } catch (const Error &e) {
     g_create_error = e.what();

@@ -12,10 +12,12 @@
 // a_0 = e^{-k|D|}/|D|, b_0 = e^{-k|D|} (kappa = 0: Laplace).  Box moments
 //   single layer  m_k  = sum_nodes s_V h^k,
 //   double layer  mK_k = sum_nodes s_K sum_i k_i n_i h^{k-e_i}
-// (the double-layer kernel is n.grad_y G) give V = sum a_k m_k and
-// K = sum a_k mK_k.  Moments are formed in FP64 for every box that some
-// target leaf accepts, directly from the box's nodes (P2M per box, one
-// launch; no upward shifts).
+// (the double-layer kernel is n.grad_y G) give V = sum_{|k|<=P} a_k m_k and
+// K = sum_{|k|<=P+1} a_k mK_k: the double-layer moment of degree |k| holds
+// h^(|k|-1), so its series is carried one degree further and both layers
+// are truncated at degree P in h.  Moments are formed in FP64: those of the
+// leaves from their nodes, those of the accepted boxes above the leaves
+// from the leaf moments by exact binomial shifts.
 #include <cmath>
 
 #include <type_traits>
@@ -68,6 +70,14 @@ constexpr double kInv4PiT = 0.07957747154594767;
 
 inline int ncoef_of(int P) { return (P + 1) * (P + 2) * (P + 3) / 6; }
 
+// coefficient counts of order P: NV single-layer terms (|k| <= P), NK
+// double-layer terms (|k| <= P + 1); a box's moments are [NV | NK]
+template <int P> struct Orders {
+  static constexpr int NV = Multi<P>::n;
+  static constexpr int NK = Multi<P + 1>::n;
+  static constexpr int NM = NV + NK;
+};
+
 // blockIdx -> task: consecutive tasks (neighbouring target leaves, similar
 // source lists) land on the same XCD so they share its L2.
 __device__ inline int xcd_task(int ntasks) {
@@ -105,15 +115,18 @@ __global__ __launch_bounds__(kP2MThreads) void k_p2m_tasks(int nf, const int *__
                                                    double *__restrict__ mom64,
                                                    float *__restrict__ mom32) {
   constexpr Multi<P> mi{};
-  constexpr int NC = Multi<P>::n;
+  constexpr Multi<P + 1> miK{};
+  constexpr int NC = Orders<P>::NV, NK = Orders<P>::NK, NM = Orders<P>::NM;
   constexpr int NW = kP2MThreads / 64;
-  __shared__ double red[NW][2 * NC];
+  __shared__ double red[NW][NM];
   const int B = tasks[3 * blockIdx.x];
   const int s0 = tasks[3 * blockIdx.x + 1], s1 = tasks[3 * blockIdx.x + 2];
   const double c[3] = {center[3 * B], center[3 * B + 1], center[3 * B + 2]};
-  double m[NC], mk[NC];
+  double m[NC], mk[NK];
 #pragma unroll
-  for (int k = 0; k < NC; ++k) m[k] = mk[k] = 0.0;
+  for (int k = 0; k < NC; ++k) m[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) mk[k] = 0.0;
   // the slice's panel records pass through LDS in tiles of kP2MTile
   // (coalesced loads, all issued together); records padded to 17 doubles
   // against bank conflicts.  A tile holds a multiple of 64 nodes, so every
@@ -162,38 +175,35 @@ __global__ __launch_bounds__(kP2MThreads) void k_p2m_tasks(int nf, const int *__
         mono[k] = mono[mi.m1[k][d]] * h[d];
       }
 #pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        m[k] += sv * mono[k];
+      for (int k = 0; k < NC; ++k) m[k] += sv * mono[k];
+      // double layer to degree P + 1 (its monomials h^(k - e_d) have
+      // degree <= P; a multi-index has the same position in both tables)
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
         double dk = 0.0;
 #pragma unroll
         for (int d = 0; d < 3; ++d)
-          if (mi.m1[k][d] >= 0) dk += mi.e[k][d] * n[d] * mono[mi.m1[k][d]];
+          if (miK.m1[k][d] >= 0) dk += miK.e[k][d] * n[d] * mono[miK.m1[k][d]];
         mk[k] += sk * dk;
       }
     }
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < NC; ++k) {
-    double a = m[k], b = mk[k];
-    for (int off = 32; off > 0; off >>= 1) {
-      a += __shfl_down(a, off, 64);
-      b += __shfl_down(b, off, 64);
-    }
-    if (lane == 0) {
-      red[wave][k] = a;
-      red[wave][NC + k] = b;
-    }
+  for (int k = 0; k < NM; ++k) {
+    double a = k < NC ? m[k] : mk[k - NC];
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+    if (lane == 0) red[wave][k] = a;
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < 2 * NC; k += kP2MThreads) {
+  for (int k = threadIdx.x; k < NM; k += kP2MThreads) {
     double v = red[0][k];
     for (int w = 1; w < NW; ++w) v += red[w][k];
     if (direct) {
-      mom64[(size_t)B * 2 * NC + k] = v;
-      if (mom32) mom32[(size_t)B * 2 * NC + k] = (float)v;
+      mom64[(size_t)B * NM + k] = v;
+      if (mom32) mom32[(size_t)B * NM + k] = (float)v;
     } else {
-      part[(size_t)blockIdx.x * 2 * NC + k] = v;
+      part[(size_t)blockIdx.x * NM + k] = v;
     }
   }
 }
@@ -235,9 +245,12 @@ __global__ __launch_bounds__(kShiftThreads) void k_shift_tasks(
     const int *__restrict__ toff, const int *__restrict__ tjq,
     const double *__restrict__ tc, double *__restrict__ mom, float *__restrict__ mom32,
     const int *__restrict__ count, double *__restrict__ part) {
-  constexpr int NC = (P + 1) * (P + 2) * (P + 3) / 6;
-  constexpr int R = (NC + kShiftThreads - 1) / kShiftThreads;
-  __shared__ double sm[kShiftLeaves * 2 * NC], sd[kShiftLeaves * NC];
+  // single-layer moments k < NC, double-layer k < NK (the terms of a
+  // coefficient reach only coefficients of lower or equal degree, so one
+  // table of degree P + 1 serves both)
+  constexpr int NC = Orders<P>::NV, NK = Orders<P>::NK, NM = Orders<P>::NM;
+  constexpr int R = (NK + kShiftThreads - 1) / kShiftThreads;
+  __shared__ double sm[kShiftLeaves * NM], sd[kShiftLeaves * NK];
   __shared__ int sL[kShiftLeaves];
   const int B = tasks[3 * blockIdx.x];
   const int la = tasks[3 * blockIdx.x + 1];
@@ -251,21 +264,21 @@ __global__ __launch_bounds__(kShiftThreads) void k_shift_tasks(
   }
   __syncthreads();
   // moments with eight loads in flight per lane
-  for (int e0 = threadIdx.x; e0 < nl * 2 * NC; e0 += 8 * kShiftThreads) {
+  for (int e0 = threadIdx.x; e0 < nl * NM; e0 += 8 * kShiftThreads) {
     double v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = e0 + u * kShiftThreads;
-      if (e < nl * 2 * NC) v[u] = mom[(size_t)sL[e / (2 * NC)] * 2 * NC + e % (2 * NC)];
+      if (e < nl * NM) v[u] = mom[(size_t)sL[e / NM] * NM + e % NM];
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = e0 + u * kShiftThreads;
-      if (e < nl * 2 * NC) sm[e] = v[u];
+      if (e < nl * NM) sm[e] = v[u];
     }
   }
-  for (int e = threadIdx.x; e < nl * NC; e += kShiftThreads) {
-    const int l = e / NC, k = e % NC;
+  for (int e = threadIdx.x; e < nl * NK; e += kShiftThreads) {
+    const int l = e / NK, k = e % NK;
     double v = 1.0;
     for (int c = 0; c < 3; ++c)
       for (int u = 0; u < monos[3 * k + c]; ++u) v *= sdl[3 * l + c];
@@ -275,7 +288,8 @@ __global__ __launch_bounds__(kShiftThreads) void k_shift_tasks(
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int k = threadIdx.x + r * kShiftThreads;
-    if (k >= NC) continue;
+    if (k >= NK) continue;
+    const bool hasV = k < NC;
     const int t0 = toff[k], t1 = toff[k + 1];
     // terms outer (one table read each), leaves inner; per-leaf sums in
     // registers are added in leaf order at the end
@@ -288,9 +302,9 @@ __global__ __launch_bounds__(kShiftThreads) void k_shift_tasks(
 #pragma unroll
       for (int l = 0; l < kShiftLeaves; ++l) {
         if (l < nl) {
-          const double c = ct * sd[l * NC + q];
-          v[l] += c * sm[l * 2 * NC + j];
-          w[l] += c * sm[l * 2 * NC + NC + j];
+          const double c = ct * sd[l * NK + q];
+          if (hasV) v[l] += c * sm[l * NM + j];
+          w[l] += c * sm[l * NM + NC + j];
         }
       }
     }
@@ -303,15 +317,15 @@ __global__ __launch_bounds__(kShiftThreads) void k_shift_tasks(
       }
     }
     if (count[B] == 1) {  // the box's only task: its moments
-      mom[(size_t)B * 2 * NC + k] = aV;
-      mom[(size_t)B * 2 * NC + NC + k] = aK;
+      if (hasV) mom[(size_t)B * NM + k] = aV;
+      mom[(size_t)B * NM + NC + k] = aK;
       if (mom32) {
-        mom32[(size_t)B * 2 * NC + k] = (float)aV;
-        mom32[(size_t)B * 2 * NC + NC + k] = (float)aK;
+        if (hasV) mom32[(size_t)B * NM + k] = (float)aV;
+        mom32[(size_t)B * NM + NC + k] = (float)aK;
       }
     } else {
-      part[(size_t)blockIdx.x * 2 * NC + k] = aV;
-      part[(size_t)blockIdx.x * 2 * NC + NC + k] = aK;
+      if (hasV) part[(size_t)blockIdx.x * NM + k] = aV;
+      part[(size_t)blockIdx.x * NM + NC + k] = aK;
     }
   }
 }
@@ -493,13 +507,13 @@ __global__ __launch_bounds__(64) void k_p2p_tasks(int ntask, const int *__restri
 
 template <class T> __device__ inline T rsqrt_t(T x);
 template <> __device__ inline float rsqrt_t<float>(float x) { return __builtin_amdgcn_rsqf(x); }
-template <> __device__ inline double rsqrt_t<double>(double x) { return 1.0 / sqrt(x); }
+template <> __device__ inline double rsqrt_t<double>(double x) { return rsqrt_fp64(x); }
 template <class T> __device__ inline T expneg_t(T nk, T kappa, T r);
 template <> __device__ inline float expneg_t<float>(float nk, float, float r) {
   return __builtin_amdgcn_exp2f(nk * r);
 }
 template <> __device__ inline double expneg_t<double>(double, double kappa, double r) {
-  return exp(-kappa * r);
+  return exp_fp64(-kappa * r);
 }
 
 template <class T, int P>
@@ -511,9 +525,9 @@ __global__ __launch_bounds__(64) void k_m2p_tasks(int ntask, const int *__restri
                                                   const T *__restrict__ tgt, int N,
                                                   T kappa, T nk,
                                                   double *__restrict__ part) {
-  constexpr Multi<P> mi{};
-  constexpr int NC = Multi<P>::n;
-  __shared__ T smom[kM2PChunkBoxes * 2 * NC];
+  constexpr Multi<P + 1> mi{};
+  constexpr int NC = Orders<P>::NV, NK = Orders<P>::NK, NM = Orders<P>::NM;
+  __shared__ T smom[kM2PChunkBoxes * NM];
   __shared__ T scen[kM2PChunkBoxes * 3];
   const int task = xcd_task(ntask);
   if (task < 0) return;
@@ -526,17 +540,17 @@ __global__ __launch_bounds__(64) void k_m2p_tasks(int ntask, const int *__restri
   __shared__ int sbox[kM2PChunkBoxes];
   if (threadIdx.x < nb) sbox[threadIdx.x] = boxes[lb + threadIdx.x];
   __syncthreads();
-  for (int e0 = threadIdx.x; e0 < nb * 2 * NC; e0 += 8 * 64) {
+  for (int e0 = threadIdx.x; e0 < nb * NM; e0 += 8 * 64) {
     T v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = e0 + 64 * u;
-      if (e < nb * 2 * NC) v[u] = mom[(size_t)sbox[e / (2 * NC)] * 2 * NC + e % (2 * NC)];
+      if (e < nb * NM) v[u] = mom[(size_t)sbox[e / NM] * NM + e % NM];
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = e0 + 64 * u;
-      if (e < nb * 2 * NC) smom[e] = v[u];
+      if (e < nb * NM) smom[e] = v[u];
     }
   }
   for (int e = threadIdx.x; e < nb * 3; e += 64) scen[e] = (T)center[3 * sbox[e / 3] + e % 3];
@@ -571,12 +585,20 @@ __global__ __launch_bounds__(64) void k_m2p_tasks(int ntask, const int *__restri
       const T ri = rsqrt_t<T>(R2);
       const T iR2 = ri * ri;
       const T ek = expneg_t<T>(nk, kappa, R2 * ri);
-      T a[NC], ay[NC], by[NC];
+      const T *m = smom + b * NM;
+      // coefficients degree by degree, each contracted as soon as it is
+      // formed (single layer k < NC, double layer k < NK), so that only the
+      // two previous degrees stay live for the recurrence
+      T a[NK], ay[NK], by[NK];
       a[0] = ri;
       by[0] = ek;
       ay[0] = ek * ri;
+      acc[0] += a[0] * m[0];
+      acc[1] += a[0] * m[NC];
+      acc[2] += ay[0] * m[0];
+      acc[3] += ay[0] * m[NC];
 #pragma unroll
-      for (int k = 1; k < NC; ++k) {
+      for (int k = 1; k < NK; ++k) {
         const int s = mi.deg[k];
         T S1 = T(0), S2 = T(0), Y1 = T(0), Y2 = T(0), B1 = T(0), B2 = T(0);
 #pragma unroll
@@ -597,13 +619,11 @@ __global__ __launch_bounds__(64) void k_m2p_tasks(int ntask, const int *__restri
         a[k] = (c1 * S1 - c2 * S2) * iR2;
         by[k] = ks * (Y1 - Y2);
         ay[k] = (c1 * Y1 - c2 * Y2 + ks * (B1 - B2)) * iR2;
-      }
-      const T *m = smom + b * 2 * NC;
-#pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        acc[0] += a[k] * m[k];
+        if (k < NC) {
+          acc[0] += a[k] * m[k];
+          acc[2] += ay[k] * m[k];
+        }
         acc[1] += a[k] * m[NC + k];
-        acc[2] += ay[k] * m[k];
         acc[3] += ay[k] * m[NC + k];
       }
     }
@@ -703,15 +723,15 @@ void launch_m2p(Tree &t, hipStream_t s, const T *mom, const T *tgt, int N, T kap
 
 template <int P>
 void launch_moments_p(Tree &t, hipStream_t s, int nf, const double *src64, float *mom32) {
-  constexpr int NC = Multi<P>::n;
+  constexpr int NM = Orders<P>::NM;
   if (t.n_mom_tasks == 0) return;
   const int direct = t.n_mom_tasks == t.nleaf;  // no leaf split into slices
   hipLaunchKernelGGL(k_p2m_tasks<P>, dim3(t.n_mom_tasks), dim3(kP2MThreads), 0, s, nf,
                      t.d_mom_task.p, t.d_center.p, src64, t.d_mom_part.p, direct, t.d_mom64.p,
                      mom32);
-  const int n = t.nbox * 2 * NC;
+  const int n = t.nbox * NM;
   if (!direct)
-    hipLaunchKernelGGL(k_mom_reduce, dim3((n + 255) / 256), dim3(256), 0, s, t.nbox, 2 * NC,
+    hipLaunchKernelGGL(k_mom_reduce, dim3((n + 255) / 256), dim3(256), 0, s, t.nbox, NM,
                        t.d_mom_first.p, t.d_mom_count.p, t.d_mom_part.p, t.d_mom64.p, mom32, 1);
   if (t.n_shift_tasks > 0) {
     hipLaunchKernelGGL(k_shift_tasks<P>, dim3(t.n_shift_tasks), dim3(kShiftThreads), 0, s,
@@ -719,7 +739,7 @@ void launch_moments_p(Tree &t, hipStream_t s, int nf, const double *src64, float
                        t.d_shift_toff.p, t.d_shift_tjq.p, t.d_shift_tc.p, t.d_mom64.p, mom32,
                        t.d_shift_count.p, t.d_shift_part.p);
     if (t.shift_multi)
-      hipLaunchKernelGGL(k_mom_reduce, dim3((n + 255) / 256), dim3(256), 0, s, t.nbox, 2 * NC,
+      hipLaunchKernelGGL(k_mom_reduce, dim3((n + 255) / 256), dim3(256), 0, s, t.nbox, NM,
                          t.d_shift_first.p, t.d_shift_count.p, t.d_shift_part.p, t.d_mom64.p,
                          mom32, 2);
   }
@@ -873,8 +893,10 @@ __global__ __launch_bounds__(64) void k_m2pT_tasks(int ntask, const int *__restr
                                                    const T *__restrict__ tgt,
                                                    const double *__restrict__ z, int N,
                                                    T kappa, T nk, double *__restrict__ Lpart) {
-  constexpr Multi<P> mi{};
-  constexpr int NC = Multi<P>::n;
+  // local coefficients to degree P + 1 (the double layer's transpose
+  // reaches them; the single layer's uses those of degree <= P)
+  constexpr Multi<P + 1> mi{};
+  constexpr int NC = Orders<P>::NK;
   const int task = xcd_task(ntask);
   if (task < 0) return;
   const int B = tasks[4 * task], lb = tasks[4 * task + 1], le = tasks[4 * task + 2];
@@ -978,8 +1000,9 @@ __global__ __launch_bounds__(64) void k_l2p(const int *__restrict__ leaves,
                                             const int *__restrict__ tslotsT, int N,
                                             double *__restrict__ part) {
   constexpr Multi<P> mi{};
-  constexpr int NC = Multi<P>::n;
-  __shared__ double lp[kMaxChain][2 * NC];
+  constexpr Multi<P + 1> miK{};
+  constexpr int NC = Orders<P>::NV, NK = Orders<P>::NK;
+  __shared__ double lp[kMaxChain][2 * NK];
   __shared__ double lc[kMaxChain][3];
   __shared__ int chain[kMaxChain];
   __shared__ int nchain;
@@ -992,9 +1015,9 @@ __global__ __launch_bounds__(64) void k_l2p(const int *__restrict__ leaves,
   }
   __syncthreads();
   const int nc = nchain;
-  for (int e = threadIdx.x; e < nc * 2 * NC; e += 64) {
-    const int a = e / (2 * NC), k = e % (2 * NC);
-    lp[a][k] = Lb[(size_t)chain[a] * 2 * NC + k];
+  for (int e = threadIdx.x; e < nc * 2 * NK; e += 64) {
+    const int a = e / (2 * NK), k = e % (2 * NK);
+    lp[a][k] = Lb[(size_t)chain[a] * 2 * NK + k];
   }
   for (int e = threadIdx.x; e < nc * 3; e += 64) lc[e / 3][e % 3] = center[3 * chain[e / 3] + e % 3];
   __syncthreads();
@@ -1014,15 +1037,17 @@ __global__ __launch_bounds__(64) void k_l2p(const int *__restrict__ leaves,
           mono[k] = mono[mi.m1[k][d]] * h[d];
         }
 #pragma unroll
-        for (int k = 0; k < NC; ++k) {
+        for (int k = 0; k < NK; ++k) {
           double dn = 0.0;
 #pragma unroll
           for (int d = 0; d < 3; ++d)
-            if (mi.m1[k][d] >= 0) dn += mi.e[k][d] * n[d] * mono[mi.m1[k][d]];
-          out[0] += lp[a][k] * mono[k];
+            if (miK.m1[k][d] >= 0) dn += miK.e[k][d] * n[d] * mono[miK.m1[k][d]];
+          if (k < NC) {
+            out[0] += lp[a][k] * mono[k];
+            out[2] += lp[a][NK + k] * mono[k];
+          }
           out[1] += lp[a][k] * dn;
-          out[2] += lp[a][NC + k] * mono[k];
-          out[3] += lp[a][NC + k] * dn;
+          out[3] += lp[a][NK + k] * dn;
         }
       }
     }
@@ -1061,7 +1086,7 @@ template <class T, int P>
 void tree_T_far(Tree &t, hipStream_t s, int nf, int N, const double *geo,
                 const double *src64, const T *src, const T *tgt, const double *z, T kappa,
                 T nk, double *part) {
-  constexpr int NC = Multi<P>::n;
+  constexpr int NK = Orders<P>::NK;
   // P2P^T
   const int nbp = ((t.n_p2pT_tasks + 7) / 8) * 8;
   if (nf == 3)
@@ -1073,8 +1098,8 @@ void tree_T_far(Tree &t, hipStream_t s, int nf, int N, const double *geo,
                        t.d_p2pT_task.p, t.d_range.p, t.d_p2pT_sub.p, src, tgt, z, geo, N,
                        kappa, nk, part);
   // M2P^T, per-box sums, L2L down the levels, L2P at the leaves
-  t.d_Lpart.reserve((size_t)std::max(1, t.n_m2pT_tasks) * 2 * NC);
-  t.d_L.reserve((size_t)t.nbox * 2 * NC);
+  t.d_Lpart.reserve((size_t)std::max(1, t.n_m2pT_tasks) * 2 * NK);
+  t.d_L.reserve((size_t)t.nbox * 2 * NK);
   if (t.n_m2pT_tasks > 0) {
     const int nbm = ((t.n_m2pT_tasks + 7) / 8) * 8;
     hipLaunchKernelGGL((k_m2pT_tasks<T, P, false>), dim3(nbm), dim3(64), 0, s,
@@ -1084,8 +1109,8 @@ void tree_T_far(Tree &t, hipStream_t s, int nf, int N, const double *geo,
                        t.n_m2pT_tasks, t.d_m2pT_task.p, t.d_m2pT_sub.p, t.d_center.p, tgt, z,
                        N, kappa, nk, t.d_Lpart.p);
   }
-  const int nl = t.nbox * 2 * NC;
-  hipLaunchKernelGGL(k_l_reduce, dim3((nl + 255) / 256), dim3(256), 0, s, t.nbox, 2 * NC,
+  const int nl = t.nbox * 2 * NK;
+  hipLaunchKernelGGL(k_l_reduce, dim3((nl + 255) / 256), dim3(256), 0, s, t.nbox, 2 * NK,
                      t.d_m2pT_count.p, t.d_m2pT_off.p, t.d_Lpart.p, t.d_L.p);
   if (nf == 3)
     hipLaunchKernelGGL((k_l2p<P, 3>), dim3(t.nleaf), dim3(64), 0, s, t.d_leaves.p,
@@ -1117,7 +1142,7 @@ void tree_T_far_p(Tree &t, hipStream_t s, int nf, int N, const double *geo,
 
 void tree_upload_exponents(Tree &t, hipStream_t s) {
   std::vector<int> ex;
-  for (int d = 0; d <= t.prm.order; ++d)
+  for (int d = 0; d <= t.prm.order + 1; ++d)
     for (int i = d; i >= 0; --i)
       for (int j = d - i; j >= 0; --j) ex.insert(ex.end(), {i, j, d - i - j});
   t.d_monos.upload(ex.data(), ex.size(), s);

@@ -602,6 +602,8 @@ void Tree::build_device(int N, int nf, const uint64_t *key, const double *geo,
                         const double *src64, hipStream_t s) {
   stream_ = s;
   ncoef = (prm.order + 1) * (prm.order + 2) * (prm.order + 3) / 6;
+  ncoefK = (prm.order + 2) * (prm.order + 3) * (prm.order + 4) / 6;
+  nmom = ncoef + ncoefK;
   Dbuf<int> owner, flag, idx;
   Dbuf<char> tmp;
   owner.alloc(N);
@@ -760,7 +762,7 @@ void Tree::build_device(int N, int nf, const uint64_t *key, const double *geo,
     d_mom_task.alloc(3 * (size_t)std::max(1, n_mom_tasks));
     hipLaunchKernelGGL(k_mom_fill, grid_for(nbox), dim3(256), 0, s, nbox, d_mom_first.p,
                        d_mom_count.p, view(), mom_chunk_panels(prm.order), d_mom_task.p);
-    d_mom_part.alloc((size_t)std::max(1, n_mom_tasks) * 2 * ncoef);
+    d_mom_part.alloc((size_t)std::max(1, n_mom_tasks) * nmom);
     // shifts of the leaf moments to the accepted boxes above them
     Dbuf<int> ls, range;
     ls.alloc(std::max(1, nleaf));
@@ -781,13 +783,13 @@ void Tree::build_device(int N, int nf, const uint64_t *key, const double *geo,
     d_shift_task.alloc(3 * (size_t)std::max(1, n_shift_tasks));
     hipLaunchKernelGGL(k_shift_fill, grid_for(nbox), dim3(256), 0, s, nbox, d_shift_first.p,
                        d_shift_count.p, range.p, kShiftLeaves, d_shift_task.p);
-    d_shift_part.alloc((size_t)std::max(1, n_shift_tasks) * 2 * ncoef);
+    d_shift_part.alloc((size_t)std::max(1, n_shift_tasks) * nmom);
     PBMP_HIP(hipStreamSynchronize(s));
     PBMP_HIP(hipGetLastError());
   }
-  d_mom64.alloc((size_t)nbox * 2 * ncoef);
-  d_mom32.alloc((size_t)nbox * 2 * ncoef);
-  PBMP_HIP(hipMemsetAsync(d_mom64.p, 0, sizeof(double) * nbox * 2 * ncoef, s));
+  d_mom64.alloc((size_t)nbox * nmom);
+  d_mom32.alloc((size_t)nbox * nmom);
+  PBMP_HIP(hipMemsetAsync(d_mom64.p, 0, sizeof(double) * nbox * nmom, s));
   tree_upload_exponents(*this, s);
   PBMP_HIP(hipStreamSynchronize(s));
 }

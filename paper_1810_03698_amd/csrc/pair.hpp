@@ -52,6 +52,43 @@ __device__ __forceinline__ void node_terms(float dx, float dy, float dz,
   ky = fmaf(er, ri2, fmaf(kappa * er, ri, ky));
 }
 
+// 1/sqrt(rr) in FP64: the hardware estimate (v_rsq_f64) refined by two
+// Newton steps y <- y + y (1 - rr y^2) / 2, each of which squares the
+// relative error, so the result is within an ulp or two of the exact
+// value; a square root and a division would take three times the
+// instructions.  rr must be positive and normal.
+__device__ __forceinline__ double rsqrt_fp64(double rr) {
+  double y = __builtin_amdgcn_rsq(rr);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-rr, y * y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+// e^x in FP64 for x <= 0 (the screening factor e^{-kappa r}; no overflow
+// or NaN handling).  Cody-Waite reduction x = n ln2 + f, |f| <= ln2/2, with
+// ln2 split into a 32-bit head (n * head is exact for |n| < 2^21) and the
+// rounded tail; e^f by its Taylor series to degree 13 (remainder below
+// 0.35^14/14! < 5e-18) in Horner form; then scaled by 2^n (e^x below the
+// smallest subnormal comes out as zero).
+__device__ __forceinline__ double exp_fp64(double x) {
+  constexpr double kLog2e = 1.4426950408889634;
+  constexpr double kLn2Hi = 0x1.62e42ffp-1;
+  constexpr double kLn2Lo = -0x1.718432a1b0e26p-35;
+  const double n = rint(x * kLog2e);
+  double f = fma(-n, kLn2Hi, x);
+  f = fma(-n, kLn2Lo, f);
+  constexpr double kFact[14] = {1.0, 1.0, 2.0, 6.0, 24.0, 120.0, 720.0, 5040.0, 40320.0,
+                                362880.0, 3628800.0, 39916800.0, 479001600.0,
+                                6227020800.0};
+  double p = 1.0 / kFact[13];
+#pragma unroll
+  for (int k = 12; k >= 0; --k) p = fma(p, f, 1.0 / kFact[k]);
+  return ldexp(p, (int)n);
+}
+
 __device__ __forceinline__ void node_terms(double dx, double dy, double dz,
                                            double kappa, double, double &vl,
                                            double &vy, double &kl, double &ky) {
@@ -60,10 +97,11 @@ __device__ __forceinline__ void node_terms(double dx, double dy, double dz,
   // a node on the target (the one-node rule on a panel's own centroid)
   // adds nothing, here and in the correction that removes it again
   const bool on = rr < kMinR2d;
-  const double rad = sqrt(rr);
-  const double ri = on ? 0.0 : 1.0 / rad;
-  const double ek = exp(-kappa * rad);
-  const double ri3 = on ? 0.0 : ri / rr;
+  const double y = rsqrt_fp64(on ? 1.0 : rr);
+  const double ri = on ? 0.0 : y;
+  const double rad = rr * y;
+  const double ek = exp_fp64(-kappa * rad);
+  const double ri3 = ri * ri * ri;
   vl = vl + ri;
   vy = vy + ek * ri;
   kl = kl + ri3;

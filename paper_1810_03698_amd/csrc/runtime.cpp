@@ -183,12 +183,6 @@ Runtime::Runtime(const pbmp_options &opt) : o(opt) {
   PBMP_REQUIRE(o.thole_a >= 0, PBMP_EARG, "thole_a >= 0");
   PBMP_REQUIRE(o.precision == PBMP_FP64 || o.precision == PBMP_MIXED, PBMP_EARG,
                "bad precision");
-  if (o.hip_stream) {
-    s_ = reinterpret_cast<hipStream_t>(o.hip_stream);
-  } else {
-    PBMP_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
-    own_stream_ = true;
-  }
   TriRule f = far_rule(o.gauss_far), nr = near_rule19();
   ru_.nf = f.n;
   ru_.nn = nr.n;
@@ -202,6 +196,13 @@ Runtime::Runtime(const pbmp_options &opt) : o(opt) {
   }
   ru_.ngl = 16;
   gauss_legendre(16, ru_.glx, ru_.glw);
+  // the first HIP call comes after the host-only set-up above
+  if (o.hip_stream) {
+    s_ = reinterpret_cast<hipStream_t>(o.hip_stream);
+  } else {
+    PBMP_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
+    own_stream_ = true;
+  }
 }
 
 void Runtime::set_options(const pbmp_options &n) {

@@ -86,7 +86,11 @@ struct TreeParams {
 class Tree {
  public:
   TreeParams prm;
-  int nbox = 0, nleaf = 0, ncoef = 0, depth = 0;
+  // coefficient counts: ncoef = C(P+3, 3) single-layer terms (|k| <= P),
+  // ncoefK = C(P+4, 3) double-layer terms (|k| <= P + 1: the double-layer
+  // moment of degree |k| holds h^(|k|-1), so both layers reach degree P in
+  // h); moments and local coefficients of a box are [ncoef | ncoefK]
+  int nbox = 0, nleaf = 0, ncoef = 0, ncoefK = 0, nmom = 0, depth = 0;
   std::vector<int> level_start;  // boxes of level l are [level_start[l], level_start[l+1])
   // tasks and list sizes
   int n_p2p_tasks = 0, n_m2p_tasks = 0, max_slots = 0;
@@ -117,23 +121,23 @@ class Tree {
   Dbuf<int> d_m2pT_sub, d_m2pT_task, d_m2pT_count, d_m2pT_off;  // off: first task of a box
   Dbuf<int> d_tslotsT;    // [N] transposed slots of the panel's leaf (tasks + 1)
   int n_p2pT_tasks = 0, n_m2pT_tasks = 0, max_slots_T = 1;
-  Dbuf<double> d_Lpart, d_L;  // local coefficients: per M2P^T task, per box [2][ncoef]
+  Dbuf<double> d_Lpart, d_L;  // local coefficients: per M2P^T task, per box [2][ncoefK]
   // moment tasks: the panels of every leaf in slices of at most
   // mom_chunk_panels(P); task = (box, s0, s1); a box's slices are consecutive
   int n_mom_tasks = 0;
   Dbuf<int> d_mom_task, d_mom_first, d_mom_count;
-  Dbuf<double> d_mom_part;  // [n_mom_tasks][2][ncoef]
+  Dbuf<double> d_mom_part;  // [n_mom_tasks][nmom]
   // shift tasks: the leaves under an accepted box with children in runs of
   // at most kShiftLeaves; task = (box, first leaf index, end leaf index)
   int n_shift_tasks = 0;
   bool shift_multi = false;  // some box has several shift tasks
   Dbuf<int> d_shift_task, d_shift_first, d_shift_count;
-  Dbuf<double> d_shift_part;  // [n_shift_tasks][2][ncoef]
+  Dbuf<double> d_shift_part;  // [n_shift_tasks][nmom]
   Dbuf<int> d_shift_toff, d_shift_tjq;  // per coefficient k: terms [toff[k], toff[k+1]), (j, k-j)
   Dbuf<double> d_shift_tc;              // C(k, j) of each term
-  Dbuf<double> d_mom64;   // [nbox][2][ncoef]
-  Dbuf<float> d_mom32;    // [nbox][2][ncoef]
-  Dbuf<int> d_monos;      // [3*ncoef] exponents
+  Dbuf<double> d_mom64;   // [nbox][nmom]
+  Dbuf<float> d_mom32;    // [nbox][nmom]
+  Dbuf<int> d_monos;      // [3*ncoefK] exponents up to degree P + 1
 
   // Build from the Morton keys of the panels in internal (sorted) order,
   // the centroids (geo SoA) and far nodes (src64 records), all on device.

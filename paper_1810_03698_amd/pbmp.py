@@ -193,6 +193,10 @@ class Solver:
             raise PbmpError(rc, self.lib.pbmp_last_error(None).decode())
         self.ctx = ctx
         self.nt = self.nv = self.m = 0
+        # advanced by every call that replaces the state a backward
+        # differentiates (mesh, sites, Stern layer, solve), so that a caller
+        # holding an earlier solve's number can tell that it is gone
+        self.state_id = 0
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -214,6 +218,7 @@ class Solver:
         nv = len(verts)
         nt = len(tris)
         v, t = _Arg(verts, np.float64, 3 * nv), _Arg(tris, np.int32, 3 * nt)
+        self.state_id += 1
         self._check(self.lib.pbmp_set_mesh(self.ctx, nv, v.ptr, nt, t.ptr,
                                            _common_where([v, t])))
         self.nt, self.nv, self.nt2 = nt, nv, 0
@@ -236,6 +241,7 @@ class Solver:
     def set_stern(self, verts, tris, eps_stern):
         """Enclosing ion-exclusion surface (see pbmp_set_stern); tris=None
         removes it."""
+        self.state_id += 1
         if tris is None:
             self._check(self.lib.pbmp_set_stern(self.ctx, 0, None, 0, None, float(eps_stern), HOST))
             self.nt2 = 0
@@ -253,6 +259,7 @@ class Solver:
                 _Arg(alpha, np.float64, m),
                 _Arg(group, np.int32, m) if group is not None else _Arg(None, None)]
         w = _common_where(args)
+        self.state_id += 1
         self._check(self.lib.pbmp_set_sites(self.ctx, m, *[a.ptr for a in args], w))
         self.m = m
 
@@ -267,6 +274,7 @@ class Solver:
                         mu_diss=np.empty((self.m, 3)), mu_vac=np.empty((self.m, 3)))
             r.phi, r.dphidn = keep["phi"].ctypes.data, keep["dphidn"].ctypes.data
             r.mu_diss, r.mu_vac = keep["mu_diss"].ctypes.data, keep["mu_vac"].ctypes.data
+        self.state_id += 1
         rc = self._check(self.lib.pbmp_solve(self.ctx, ctypes.byref(r)), allow_warn=True)
         out = dict(status=rc, dG=r.dG_kcal, dG_solv=r.dG_solv_kcal,
                    dG_pol=r.dG_pol_kcal, G_vac=r.G_vac_kcal, scf_iters=r.scf_iters,

@@ -29,3 +29,18 @@ def say(capsys):
         with capsys.disabled():
             print(*args, flush=True)
     return _say
+
+
+@pytest.fixture(scope="module")
+def say_module(request):
+    """`say` for module-scoped fixtures (no capsys there): writes to the
+    terminal reporter, which pytest does not capture."""
+    tr = request.config.pluginmanager.get_plugin("terminalreporter")
+
+    def _say(*args):
+        line = " ".join(str(a) for a in args)
+        if tr is not None:
+            tr.write_line(line)
+        else:
+            print(line, flush=True)
+    return _say

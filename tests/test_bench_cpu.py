@@ -8,14 +8,16 @@ def _m2p_count_by_terms(order):
     # the same count written term by term from the recurrence: per
     # coefficient k != 0, three sums over the first-lower neighbours
     # (a product each, an addition between consecutive ones), three over the
-    # second-lower ones (additions only), then the combination; four moment
-    # products and sums per coefficient; 14 for the pair set-up
+    # second-lower ones (additions only), then the combination; the
+    # recurrence runs to degree P + 1 (the double layer's series); four
+    # moment products and sums per coefficient of degree <= P, two of degree
+    # P + 1; 14 for the pair set-up
     total = 14
-    for s in range(order + 1):
+    for s in range(order + 2):
         for i in range(s + 1):
             for j in range(s - i + 1):
                 k = (i, j, s - i - j)
-                total += 4 * 2
+                total += (4 if s <= order else 2) * 2
                 if s == 0:
                     continue
                 first = [d for d in range(3) if k[d] >= 1]
@@ -32,8 +34,8 @@ def _m2p_count_by_terms(order):
 
 
 def test_m2p_flops():
-    assert bench._m2p_flops(4) == 955
-    assert bench._m2p_flops(5) == 1630
+    assert bench._m2p_flops(4) == 1546
+    assert bench._m2p_flops(5) == 2451
     for P in range(1, 8):
         assert bench._m2p_flops(P) == _m2p_count_by_terms(P)
 

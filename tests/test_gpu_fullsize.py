@@ -6,15 +6,24 @@ The FP64 oracle cannot run a whole product at these sizes, so it evaluates
 sampled rows one at a time: operator-product rows, right-hand-side entries
 and site fields.  Whole-solve results are checked through properties that
 hold at any size: the mixed path against the FP64 path of the same method
-(relative 1e-4 on the energy), and the treecode energy against the direct
-sum (relative 1e-5 at P = 5, 2e-5 at P = 4 -- the treecode's own accuracy,
-measured against the oracle on the smaller cases).
+(relative 1e-4 on the energy), and the FP64 treecode energy against the
+FP64 direct solve (relative 1e-5).
+
+Checks that take several minutes each on one GPU (the FP64 direct solve
+of the 5000-atom globule, per-atom finite differences on it, the full
+binding triad) run only with PBMP_LONG_TESTS=1; their last results are
+recorded in profiles/fullsize_checks.md.
 
 Bars on sampled rows (max-norm error over the sample divided by the
-sample's max-norm): direct mixed 2e-5 (FP32 far field); treecode 1e-3 at
-P = 4 and 5e-4 at P = 5 (its 2-norm error is 2-4e-4 at P = 4 on the
-5120-panel sphere against the full oracle product; a max-norm over a
-sample sits above that)."""
+sample's max-norm): direct mixed 2e-5 (FP32 far field); treecode against
+the oracle's direct operator 5e-4 at P = 4 and 2e-4 at P = 5 (the
+treecode's own approximation; its 2-norm error is ~1e-4 at P = 4 on the
+5120-panel sphere against the full oracle product, and a max-norm over a
+sample sits above that), against the oracle's treecode product 1e-12
+(FP64) and 2e-5 (mixed)."""
+
+import os
+import time
 
 import numpy as np
 import pytest
@@ -25,6 +34,10 @@ from synth import workload
 pytestmark = pytest.mark.gpu
 
 FULL = ["sphere_81920", "globule_1000", "globule_5000", "binding_complex"]
+LONG = os.environ.get("PBMP_LONG_TESTS") == "1"
+long_only = pytest.mark.skipif(
+    not LONG, reason="several minutes on one GPU: run with PBMP_LONG_TESTS=1 "
+                     "(results recorded in profiles/fullsize_checks.md)")
 ROWS = 40
 SITES = 24
 
@@ -79,24 +92,45 @@ def _bar(w, mode, kind):
     if mode == "direct":
         return 2e-5
     P = int(w["params"].get("order_P", 4))
-    return 1e-3 if P <= 4 else 5e-4
+    return 5e-4 if P <= 4 else 2e-4
 
 
 @pytest.mark.parametrize("name", FULL)
-def test_fullsize_matvec_rows(name):
+def test_fullsize_matvec_rows(name, say):
+    """Sampled rows of the product in the benchmark's configuration against
+    the oracle's direct operator (at the treecode's accuracy), and, for the
+    treecode workloads, against the oracle's treecode product on the same
+    octree (FP64 to rounding, mixed to the FP32 far field)."""
     w, m = _work(name)
     p = w["params"]
-    print("case", name, "panels", m.N, flush=True)
+    say("case", name, "panels", m.N)
     s = _solver(w)
     rows = np.sort(np.random.default_rng(7).choice(m.N, ROWS, replace=False))
-    for kind, x in _densities(m, 3).items():
+    xs = _densities(m, 3)
+    for kind, x in xs.items():
         y = s.matvec(x)
         got = np.concatenate([y[rows], y[m.N + rows]])
         ref = _oracle_rows(m, x, rows, p["eps_in"], p["eps_out"])
         err = np.abs(got - ref).max() / np.abs(ref).max()
-        print(name, kind, p["mode"], "sampled-row error", err, flush=True)
+        say(name, kind, p["mode"], "sampled-row error vs direct operator", err)
         assert err < _bar(w, p["mode"], kind)
     s.close()
+    if p["mode"] != "treecode":
+        return
+    from oracle import treecode
+    t0 = time.perf_counter()
+    tc = treecode.Treecode(m, p["theta"], int(p["order_P"]), int(p["leaf_panels"]))
+    x = xs["random"]
+    ref = tc.matvec(x, p["eps_in"], p["eps_out"], rows=rows)
+    say(name, "oracle treecode rows %.1f s" % (time.perf_counter() - t0))
+    for precision, tol in (("fp64", 1e-12), ("mixed", 2e-5)):
+        s = _solver(w, precision=precision)
+        y = s.matvec(x)
+        s.close()
+        got = np.concatenate([y[rows], y[m.N + rows]])
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        say(name, precision, "sampled-row error vs oracle treecode", err)
+        assert err < tol
 
 
 def test_fullsize_direct_matvec_rows():
@@ -135,86 +169,156 @@ def test_fullsize_rhs_and_site_fields(name):
         assert e < 2e-5, (k, e)
 
 
+def _solve(w, say, label, **kw):
+    t0 = time.perf_counter()
+    r = _solver(w, gmres_restart=100, gmres_maxit=20000, **kw).solve(outputs=False)
+    say(label, "status", r["status"], "scf", r["scf_iters"], "gmres", r["gmres_iters"],
+        "relres", r["relres"], "dG", r["dG"], "%.1f s" % (time.perf_counter() - t0))
+    assert r["status"] == 0
+    return r
+
+
 @pytest.mark.parametrize("name", ["sphere_81920", "globule_1000", "globule_5000"])
-def test_fullsize_energy_properties(name):
-    """Mixed vs FP64 on the same method, and treecode vs direct."""
+def test_fullsize_energy_properties(name, say):
+    """Mixed vs FP64 on the same method (relative 1e-4); where the workload
+    uses the treecode, the FP64 treecode energy against the FP64 direct
+    solve (relative 1e-5; on the 5000-atom globule that direct solve is a
+    long check of its own)."""
     w, m = _work(name)
-    print(name, "mixed solve", flush=True)
-    rm = _solver(w, gmres_restart=100, gmres_maxit=8000).solve(outputs=False)
-    print(name, "status", rm["status"], "scf", rm["scf_iters"], "gmres", rm["gmres_iters"],
-          "relres", rm["relres"], flush=True)
-    print(name, "fp64 solve", flush=True)
-    r64 = _solver(w, precision="fp64", gmres_restart=100, gmres_maxit=8000).solve(outputs=False)
-    print(name, "status", r64["status"], "scf", r64["scf_iters"], "gmres", r64["gmres_iters"],
-          "relres", r64["relres"], flush=True)
+    rm = _solve(w, say, name + " mixed")
+    r64 = _solve(w, say, name + " fp64", precision="fp64")
     rel = abs(rm["dG"] - r64["dG"]) / abs(r64["dG"])
-    print(name, "dG mixed", rm["dG"], "fp64", r64["dG"], "rel", rel, flush=True)
-    assert rm["status"] == 0 and r64["status"] == 0
+    say(name, "dG mixed vs fp64", rel)
     assert rel < 1e-4
-    if w["params"]["mode"] == "treecode":
-        print(name, "direct solve", flush=True)
-        rd = _solver(w, precision="mixed", mode="direct", gmres_restart=100,
-                     gmres_maxit=8000).solve(outputs=False)
+    if w["params"]["mode"] == "treecode" and name != "globule_5000":
+        rd = _solve(w, say, name + " fp64 direct", precision="fp64", mode="direct")
         rel_t = abs(r64["dG"] - rd["dG"]) / abs(rd["dG"])
-        P = int(w["params"]["order_P"])
-        print(name, "dG tree fp64", r64["dG"], "direct mixed", rd["dG"], "rel", rel_t)
-        assert rel_t < (2e-5 if P <= 4 else 1e-5) + 1e-6
+        say(name, "dG fp64 treecode vs fp64 direct", rel_t)
+        assert rel_t < 1e-5
 
 
-def test_fullsize_gradients_fd_globule_5000(say):
-    """The 5000-atom globule (treecode, P = 5): adjoint gradients of the
-    solvation energy for 4 seeded atoms against central differences
-    (h = 1e-4 A) along a random direction per atom.  FP64 state: the base
-    solved in stages of tightening tolerance (each warm-started from the
-    last), every displaced solve warm-started from the last one, all to a
-    GMRES tolerance of 1e-14: the energy error of a solve is about the
-    adjoint times the residual, and at 1e-12 it still moved these
-    differences by ~5e-4 (1e-5 on the 1000-atom globule, where 1e-14 brings
-    the agreement to 1e-8..1e-6).  The adjoint differentiates that FP64
-    state with mixed-precision transposed solves at 1e-8 (precision switched
-    after the solve; their FP64 refinement holds the tolerance)."""
+@long_only
+def test_fullsize_treecode_vs_fp64_direct_globule_5000(say):
+    """The 5000-atom globule (theta 0.5, P 5): FP64 treecode energy against
+    the FP64 direct solve, relative 1e-5."""
     w, m = _work("globule_5000")
+    r64 = _solve(w, say, "globule_5000 fp64 treecode", precision="fp64")
+    rd = _solve(w, say, "globule_5000 fp64 direct", precision="fp64", mode="direct")
+    rel_t = abs(r64["dG"] - rd["dG"]) / abs(rd["dG"])
+    say("globule_5000 dG fp64 treecode vs fp64 direct", rel_t)
+    assert rel_t < 1e-5
+
+
+def _fd_state(name, say, mixed_adjoint=True):
+    """FP64 base state of a globule (treecode) solved to GMRES 1e-14 / SCF
+    1e-12 D in stages of tightening tolerance (each warm-started from the
+    last: the energy error of a solve is about the adjoint times its
+    residual, and central differences at h = 1e-4 A need it below ~1e-9
+    kcal/mol), and its adjoint gradients (mixed-precision transposed solves
+    at 1e-8 whose FP64 refinement holds the tolerance, precision switched
+    after the solve; or FP64 ones).  The gradient checks below share it and
+    leave the solver at the base tolerances."""
+    w, m = _work(name)
     s = _solver(w, precision="fp64", gmres_restart=100, gmres_maxit=20000, scf_maxit=500,
                 warm_start=True)
-    for gtol, stol in ((1e-6, 1e-6), (1e-9, 1e-8), (1e-12, 1e-11), (1e-14, 1e-12)):
+    t0 = time.perf_counter()
+    for gtol, stol in ((1e-6, 1e-6), (1e-10, 1e-9), (1e-14, 1e-12)):
         s.set_options(gmres_tol=gtol, scf_tol_debye=stol)
         base = s.solve(outputs=False)
-        say("base stage", gtol, base["dG"], base["status"], base["scf_iters"],
-            base["gmres_iters"])
+        say(name, "base stage", gtol, base["dG"], base["status"], base["scf_iters"],
+            base["gmres_iters"], "%.1f s" % (time.perf_counter() - t0))
         assert base["status"] == 0
     # the adjoint's operator is the exact transpose of the solve's
     rng0 = np.random.default_rng(21)
     x, z = rng0.normal(size=2 * m.N), rng0.normal(size=2 * m.N)
     lhs, rhs = z @ s.matvec(x), s.matvec(z, transpose=True) @ x
-    say("transpose check", lhs, rhs, abs(lhs - rhs) / (np.linalg.norm(z) * np.linalg.norm(x)))
+    say(name, "transpose check", abs(lhs - rhs) / (np.linalg.norm(z) * np.linalg.norm(x)))
     assert abs(lhs - rhs) < 1e-12 * np.linalg.norm(z) * np.linalg.norm(x)
-    s.set_options(precision="mixed", gmres_tol=1e-8)
+    s.set_options(precision="mixed" if mixed_adjoint else "fp64", gmres_tol=1e-8)
     g = s.backward(1.0, verts=False)
-    say("backward", "status", g["status"])
+    say(name, "backward", "status", g["status"], "%.1f s" % (time.perf_counter() - t0))
     assert g["status"] == 0
     s.set_options(precision="fp64", gmres_tol=1e-14, scf_tol_debye=1e-12)
+    return dict(w=w, m=m, s=s, g=g, dG=base["dG"], name=name)
+
+
+@pytest.fixture(scope="module")
+def g1000(say_module):
+    st = _fd_state("globule_1000", say_module)
+    yield st
+    st["s"].close()
+
+
+@pytest.fixture(scope="module")
+def g5000(say_module):
+    st = _fd_state("globule_5000", say_module)
+    yield st
+    st["s"].close()
+
+
+def _energy_at(st, say, label, xyz=None, q=None, d=None, Q9=None):
+    w, s = st["w"], st["s"]
+    t0 = time.perf_counter()
+    s.set_sites(w["xyz"] if xyz is None else xyz, w["q"] if q is None else q,
+                w["d"] if d is None else d, w["Q9"] if Q9 is None else Q9, w["alpha"])
+    r = s.solve(outputs=False)
+    say(st["name"], label, r["dG"], r["status"], r["scf_iters"], r["gmres_iters"],
+        "%.1f s" % (time.perf_counter() - t0))
+    assert r["status"] == 0
+    return r["dG"]
+
+
+GRAD_ATOMS = 20
+
+
+def _joint_position_check(st, say):
+    """Adjoint position gradients of 20 seeded atoms against a central
+    difference (h = 1e-4 A) along one joint random direction U that moves
+    all 20 atoms at once (unit norm over the 60 coordinates): the adjoint
+    gives sum_l g_l . U_l, the difference (E(+hU) - E(-hU)) / 2h; plain
+    relative error below 1e-4."""
+    w, g = st["w"], st["g"]
     rng = np.random.default_rng(20)
-    atoms = np.sort(rng.choice(len(w["q"]), 4, replace=False))
+    atoms = np.sort(rng.choice(len(w["q"]), GRAD_ATOMS, replace=False))
+    U = np.zeros_like(w["xyz"])
+    U[atoms] = rng.normal(size=(GRAD_ATOMS, 3))
+    U /= np.linalg.norm(U)
     h = 1e-4
-    gmax = np.abs(g["xyz"]).max()
+    st["s"].set_options(gmres_tol=1e-14, scf_tol_debye=1e-12)
+    e = [_energy_at(st, say, "joint %+g" % sg, xyz=w["xyz"] + sg * h * U) for sg in (1.0, -1.0)]
+    fd = (e[0] - e[1]) / (2 * h)
+    an = float(np.sum(g["xyz"] * U))
+    rel = abs(an - fd) / abs(fd)
+    say(st["name"], "joint direction over 20 atoms: adjoint", an, "fd", fd, "rel", rel)
+    assert rel < 1e-4
+
+
+def _per_atom_position_check(st, say, atoms_slice=slice(None)):
+    """Per atom, for the 20 seeded atoms (or a slice of them): central
+    difference (h = 1e-4 A) along a random unit direction u_l against
+    g_l . u_l.  The error is taken relative to |g_l|, the norm of the atom's
+    gradient (a random direction can be nearly orthogonal to it, so
+    |g_l . u_l| has no floor); bar 1e-4."""
+    w, g = st["w"], st["g"]
+    rng = np.random.default_rng(23)
+    atoms = np.sort(rng.choice(len(w["q"]), GRAD_ATOMS, replace=False))
+    dirs = rng.normal(size=(GRAD_ATOMS, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    h = 1e-4
+    st["s"].set_options(gmres_tol=1e-14, scf_tol_debye=1e-12)
     worst = 0.0
-    for l in atoms:
-        u = rng.normal(size=3)
-        u /= np.linalg.norm(u)
+    for l, u in list(zip(atoms, dirs))[atoms_slice]:
         e = []
-        for sign in (1.0, -1.0):
+        for sg in (1.0, -1.0):
             xyz = w["xyz"].copy()
-            xyz[l] += sign * h * u
-            s.set_sites(xyz, w["q"], w["d"], w["Q9"], w["alpha"])
-            r = s.solve(outputs=False)
-            assert r["status"] == 0
-            e.append(r["dG"])
+            xyz[l] += sg * h * u
+            e.append(_energy_at(st, say, "atom %d %+g" % (l, sg), xyz=xyz))
         fd = (e[0] - e[1]) / (2 * h)
         an = g["xyz"][l] @ u
-        err = abs(an - fd) / max(abs(fd), 1e-2 * gmax)
+        err = abs(an - fd) / np.linalg.norm(g["xyz"][l])
         worst = max(worst, err)
-        say("atom", l, "adjoint", an, "fd", fd, "rel", err)
-    s.close()
+        say(st["name"], "atom", l, "adjoint", an, "fd", fd, "|g_l|",
+            np.linalg.norm(g["xyz"][l]), "err/|g_l|", err)
     assert worst < 1e-4
 
 
@@ -225,52 +329,72 @@ def _traceless(rng, n):
     return A.reshape(n, 9)
 
 
-def test_fullsize_multipole_gradients_fd_globule_5000(say):
+def _multipole_check(st, say):
     """Gradients with respect to the charges, dipoles and quadrupoles of 20
-    seeded atoms of the 5000-atom globule (treecode, P = 5) against central
-    differences, one random direction per kind over all 20 atoms.  The
-    solvation energy is a homogeneous quadratic form in the permanent
-    multipoles (the right-hand side, the induced dipoles and the reaction
-    potentials are linear in them and the energy pairs two such quantities),
-    so a central difference is exact at any step: the step is large (0.5
-    along a unit direction) and only the solve tolerance limits the
-    agreement.  FP64 state at GMRES 1e-10 (its energy is within ~3e-6
-    kcal/mol of the 1e-14 one), differentiated by mixed transposed solves
-    at 1e-8 (the gradient's error follows the adjoint's, far below the
-    bar)."""
-    w, m = _work("globule_5000")
-    s = _solver(w, precision="fp64", gmres_restart=100, gmres_maxit=20000, scf_maxit=500,
-                warm_start=True)
-    for gtol, stol in ((1e-6, 1e-6), (1e-10, 1e-9)):
-        s.set_options(gmres_tol=gtol, scf_tol_debye=stol)
-        base = s.solve(outputs=False)
-        say("base stage", gtol, base["dG"], base["status"], base["scf_iters"],
-            base["gmres_iters"])
-        assert base["status"] == 0
-    s.set_options(precision="mixed", gmres_tol=1e-8)
-    g = s.backward(1.0, verts=False)
-    say("backward status", g["status"])
-    assert g["status"] == 0
-    s.set_options(precision="fp64", gmres_tol=1e-10, scf_tol_debye=1e-9)
+    seeded atoms against central differences, one random direction per kind
+    over all 20 atoms.  The solvation energy is a homogeneous quadratic form
+    in the permanent multipoles (the right-hand side, the induced dipoles
+    and the reaction potentials are linear in them and the energy pairs two
+    such quantities), so a central difference is exact at any step: the
+    step is large (0.5 along a unit direction) and only the solve tolerance
+    limits the agreement (displaced solves at GMRES 1e-11, SCF 1e-10 D)."""
+    w, g, s = st["w"], st["g"], st["s"]
+    s.set_options(gmres_tol=1e-11, scf_tol_debye=1e-10)
     rng = np.random.default_rng(22)
-    atoms = np.sort(rng.choice(len(w["q"]), 20, replace=False))
+    atoms = np.sort(rng.choice(len(w["q"]), GRAD_ATOMS, replace=False))
     h = 0.5
     for kind, width in (("q", 1), ("d", 3), ("Q9", 9)):
         U = np.zeros((len(w["q"]), width))
-        U[atoms] = _traceless(rng, 20) if kind == "Q9" else rng.normal(size=(20, width))
+        U[atoms] = _traceless(rng, GRAD_ATOMS) if kind == "Q9" else \
+            rng.normal(size=(GRAD_ATOMS, width))
         U = U.reshape(w[kind].shape) / np.linalg.norm(U)
-        e = []
-        for sign in (1.0, -1.0):
-            mp_ = {k: w[k] for k in ("q", "d", "Q9")}
-            mp_[kind] = w[kind] + sign * h * U
-            s.set_sites(w["xyz"], mp_["q"], mp_["d"], mp_["Q9"], w["alpha"])
-            r = s.solve(outputs=False)
-            say(kind, sign, r["dG"], r["status"], r["scf_iters"], r["gmres_iters"])
-            assert r["status"] == 0
-            e.append(r["dG"])
+        e = [_energy_at(st, say, "%s %+g" % (kind, sg), **{kind: w[kind] + sg * h * U})
+             for sg in (1.0, -1.0)]
         fd = (e[0] - e[1]) / (2 * h)
         an = float(np.sum(g[kind] * U))
         rel = abs(an - fd) / abs(fd)
-        say(kind, "adjoint", an, "fd", fd, "rel", rel)
+        say(st["name"], kind, "adjoint", an, "fd", fd, "rel", rel)
         assert rel < 1e-4
-    s.close()
+    s.set_options(gmres_tol=1e-14, scf_tol_debye=1e-12)
+
+
+# The 1000-atom globule (about 30k panels, theta 0.5, P 4): the gradient
+# checks of the workload definition, in the main suite (the per-atom
+# differences of all 20 atoms as a long check).
+def test_position_gradient_fd_joint_globule_1000(g1000, say):
+    _joint_position_check(g1000, say)
+
+
+def test_position_gradient_fd_per_atom_globule_1000(g1000, say):
+    """The first 4 of the 20 seeded atoms (all 20: a long check)."""
+    _per_atom_position_check(g1000, say, slice(0, 4))
+
+
+@long_only
+def test_position_gradient_fd_all_atoms_globule_1000(g1000, say):
+    _per_atom_position_check(g1000, say, slice(4, None))
+
+
+def test_multipole_gradients_fd_globule_1000(g1000, say):
+    _multipole_check(g1000, say)
+
+
+# The 5000-atom globule (about 150k panels, theta 0.5, P 5): the same
+# checks, several minutes each (each displaced solve to GMRES 1e-14 takes
+# about a minute on one GPU).  PBMP_LONG_ATOMS=a:b restricts the per-atom
+# check to atoms a..b-1 of the 20, so that it can be spread over runs.
+@long_only
+def test_position_gradient_fd_joint_globule_5000(g5000, say):
+    _joint_position_check(g5000, say)
+
+
+@long_only
+def test_position_gradient_fd_per_atom_globule_5000(g5000, say):
+    sel = os.environ.get("PBMP_LONG_ATOMS", "")
+    sl = slice(*(int(v) for v in sel.split(":"))) if sel else slice(None)
+    _per_atom_position_check(g5000, say, sl)
+
+
+@long_only
+def test_multipole_gradients_fd_globule_5000(g5000, say):
+    _multipole_check(g5000, say)

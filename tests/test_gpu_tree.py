@@ -1,11 +1,17 @@
-"""GPU treecode (P2M/M2M, P2P over leaf lists, M2P Taylor expansions)
-against the FP64 CPU oracle's direct product, through the C-ABI.
+"""GPU treecode (P2M and moment shifts, P2P over leaf lists, M2P Taylor
+expansions) through the C-ABI, against the FP64 CPU oracle.
 
-The treecode approximates the far field; its error is controlled by the
-acceptance parameter theta and the Taylor order P.  Bars: the operator
-product's error falls with P (measured at theta = 0.5: ~1e-3, ~2-4e-4,
-~2e-5 relative for P = 2, 4, 6); the solvation energy agrees with the
-direct result to 2e-5 at P = 4 and 1e-5 at P = 5 (FP64), 1e-4 mixed."""
+Exact parity: the library's FP64 treecode product equals the oracle's
+treecode product (``oracle.treecode``: the same octree and lists, Taylor
+coefficients from power series instead of the recurrences, moments from
+the nodes instead of shifts) to rounding, element by element, at P = 4, 5
+and 6 and leaf sizes 64 and 300; the mixed-precision product to the FP32
+far field's accuracy (2e-5 of the largest entry).
+
+Approximation: against the oracle's direct product the treecode error
+falls with P, and the solvation energy of the treecode solve agrees with
+the FP64 direct solve to 1e-5 (FP64 treecode, theta = 0.5, P = 4 and 5)
+and 1e-4 (mixed precision)."""
 
 import numpy as np
 import pytest
@@ -45,6 +51,51 @@ def oracle_product(sph5120):
                "smooth": (xs, bie.matvec(m, xs, 1.0, 80.0))}
 
 
+@pytest.fixture(scope="module")
+def ragged_case():
+    from tests.test_gpu_direct import _ragged
+    return _ragged()
+
+
+@pytest.mark.parametrize("name,leaf,P", [("sphere_5120", 64, 4), ("sphere_5120", 64, 5),
+                                         ("sphere_5120", 64, 6), ("sphere_5120", 300, 4),
+                                         ("sphere_5120", 300, 5), ("ragged", 50, 4)])
+def test_tree_product_matches_oracle_treecode(name, leaf, P, sph5120, ragged_case):
+    """Element by element against the oracle's treecode product on 256
+    sampled rows (all rows of the ragged molecule)."""
+    from oracle import treecode
+    w = sph5120 if name == "sphere_5120" else ragged_case
+    m = bie.Mesh(w["verts"], w["tris"], 0.125)
+    rng = np.random.default_rng(41)
+    x = rng.normal(size=2 * m.N)
+    rows = np.arange(m.N) if m.N <= 1024 else np.sort(rng.choice(m.N, 256, replace=False))
+    ref = treecode.Treecode(m, 0.5, P, leaf).matvec(x, 1.0, 80.0, rows=rows)
+    for precision, tol in (("fp64", 1e-12), ("mixed", 2e-5)):
+        s = _solver(w, precision=precision, order_P=P, leaf_panels=leaf)
+        y = s.matvec(x)
+        got = np.concatenate([y[:m.N][rows], y[m.N:][rows]])
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(name, leaf, P, precision, "max error / max entry", err)
+        s.close()
+        assert err < tol
+
+
+@pytest.mark.parametrize("leaf", [64, 300])
+def test_tree_theta_small_equals_direct_all_variants(leaf, sph5120, oracle_product):
+    """theta -> 0 accepts no box: the treecode is the direct sum over leaf
+    pairs.  At leaf 300 the P2P tasks take 3 to 5 targets per lane and
+    several lane groups; FP64 to rounding, mixed to the FP32 far field."""
+    m, cases = oracle_product
+    x, ref = cases["random"]
+    for precision, tol in (("fp64", 1e-12), ("mixed", 2e-5)):
+        s = _solver(sph5120, theta=1e-6, leaf_panels=leaf, precision=precision)
+        y = s.matvec(x)
+        err = np.abs(y - ref).max() / np.abs(ref).max()
+        print(leaf, precision, err)
+        s.close()
+        assert err < tol
+
+
 def test_tree_matvec_error_falls_with_order(sph5120, oracle_product):
     m, cases = oracle_product
     errs = {}
@@ -58,10 +109,10 @@ def test_tree_matvec_error_falls_with_order(sph5120, oracle_product):
     for name in cases:
         assert errs[(4, name)] < errs[(2, name)] / 3
         assert errs[(6, name)] < errs[(4, name)] / 3
-        assert errs[(4, name)] < 5e-4 and errs[(6, name)] < 5e-5
+        assert errs[(4, name)] < 2e-4 and errs[(6, name)] < 3e-5
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 5e-4), ("mixed", 5e-4)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 2e-4), ("mixed", 2e-4)])
 def test_tree_matvec_p4_vs_oracle(precision, tol, sph5120, oracle_product):
     m, cases = oracle_product
     s = _solver(sph5120, precision=precision)
@@ -72,25 +123,18 @@ def test_tree_matvec_p4_vs_oracle(precision, tol, sph5120, oracle_product):
         assert err < tol
 
 
-def test_tree_theta_small_equals_direct(sph5120, oracle_product):
-    """theta -> 0 accepts no box: the treecode reduces to the direct sum over
-    leaf pairs (FP64 parity to rounding)."""
-    m, cases = oracle_product
-    s = _solver(sph5120, theta=1e-6)
-    x, ref = cases["random"]
-    y = s.matvec(x)
-    assert np.abs(y - ref).max() < 1e-12 * np.abs(ref).max()
-
-
-def test_tree_solve_energy(sph5120):
+@pytest.mark.parametrize("leaf", [64, 300])
+def test_tree_solve_energy(leaf, sph5120):
+    """Solvation energy of the treecode solve against the FP64 direct solve
+    (theta = 0.5): 1e-5 in FP64 at P = 4 and 5, 1e-4 in mixed precision."""
     w = sph5120
     direct = _solver(w, mode="direct", gmres_tol=1e-10, scf_tol_debye=1e-9).solve()
-    for precision, P, tol in (("fp64", 4, 2e-5), ("fp64", 5, 1e-5),
+    for precision, P, tol in (("fp64", 4, 1e-5), ("fp64", 5, 1e-5),
                               ("mixed", 4, 1e-4)):
         tree = _solver(w, precision=precision, order_P=P, gmres_tol=1e-10,
-                       scf_tol_debye=1e-9).solve()
+                       scf_tol_debye=1e-9, leaf_panels=leaf).solve()
         rel = abs(tree["dG"] - direct["dG"]) / abs(direct["dG"])
-        print(precision, P, tree["dG"], direct["dG"], rel)
+        print(precision, P, leaf, tree["dG"], direct["dG"], rel)
         assert rel < tol
 
 
@@ -106,7 +150,7 @@ def test_tree_on_ragged_molecule():
         y = s.matvec(x)
         err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
         print(precision, err)
-        assert err < 5e-4
+        assert err < 2e-4
 
 
 def _tree_sets(t):
@@ -198,7 +242,7 @@ def test_tree_transpose_vs_oracle(sph5120):
         y = s.matvec(z, transpose=True)
         err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
         print(precision, "transpose error", err)
-        assert err < 5e-4
+        assert err < 2e-4
 
 
 @pytest.mark.parametrize("P", [4, 5])
