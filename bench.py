@@ -81,14 +81,14 @@ PEAK_FP64_VECTOR = 78.6  # TFLOP/s, MI355X published
 # and precision whose solvation energy is within 5e-5 relative of the
 # reference (half the 1e-4 target, a margin for other meshes of the same
 # class); from `python bench.py --calibrate --workload W` (every pair of
-# GMRES 1e-3..1e-6 and SCF 1e-1..1e-4 D; the fastest that qualifies).
+# GMRES 1e-4..1e-6 and SCF 1e-2..1e-4 D; the fastest that qualifies).
 SOLVE_TOL = {
-    ("globule_5000", "mixed"): (1e-6, 1e-6),
-    ("globule_5000", "fp64"): (1e-6, 1e-6),
+    ("globule_5000", "mixed"): (1e-5, 1e-3),
+    ("globule_5000", "fp64"): (1e-5, 1e-3),
 }
 REF_TOL = (1e-10, 1e-9)
-CAL_GMRES = (1e-3, 1e-4, 1e-5, 1e-6)
-CAL_SCF = (1e-1, 1e-2, 1e-3, 1e-4)
+CAL_GMRES = (1e-4, 1e-5, 1e-6)
+CAL_SCF = (1e-2, 1e-3, 1e-4)
 
 
 def _m2p_flops(order):
@@ -192,7 +192,12 @@ def _cpu_model():
     return None
 
 
-def _make_solver(w, mode, precision, stream, dev, gmres_tol, scf_tol):
+def _progress(*args):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(*args, file=sys.stderr, flush=True)
+
+
+def _make_solver(w, mode, precision, stream, dev, gmres_tol, scf_tol, warm_start=False):
     import torch
     from paper_1810_03698_amd import Solver
     p = w["params"]
@@ -204,7 +209,7 @@ def _make_solver(w, mode, precision, stream, dev, gmres_tol, scf_tol):
                gmres_restart=int(p["gmres_restart"]), gmres_tol=gmres_tol,
                gmres_maxit=20000, scf_tol_debye=scf_tol, scf_omega=p["scf_omega"],
                scf_maxit=500, thole_a=p["thole_a"], precision=precision,
-               stream=stream.cuda_stream)
+               stream=stream.cuda_stream, warm_start=warm_start)
     t = lambda a, dt=torch.float64: torch.as_tensor(a, dtype=dt, device=dev).contiguous()
     s.set_mesh(t(w["verts"]), t(w["tris"], torch.int32))
     s.set_sites(t(w["xyz"]), t(w["q"]), t(w["d"]), t(w["Q9"]), t(w["alpha"]))
@@ -220,13 +225,27 @@ def _timed_solve(s):
     return r, 1e3 * (time.perf_counter() - t0)
 
 
+def reference_solve(w, mode, stream, dev):
+    """The reference energy: FP64 solves tightened in stages to REF_TOL, each
+    starting from the last one's solution and dipoles (the stages only
+    shorten the way to the same fixed point)."""
+    s = _make_solver(w, mode, "fp64", stream, dev, 1e-6, 1e-6, warm_start=True)
+    total = 0.0
+    for gt, st in ((1e-6, 1e-6), (1e-8, 1e-7), REF_TOL):
+        s.set_options(gmres_tol=gt, scf_tol_debye=st)
+        r, ms = _timed_solve(s)
+        total += ms
+        _progress("reference stage", gt, st, "dG", r["dG"], "gmres", r["gmres_iters"],
+                  "scf", r["scf_iters"], "%.0f ms" % ms)
+    s.close()
+    return r, total
+
+
 def calibrate(w, mode, stream, dev, args):
     """Every (GMRES, SCF) tolerance pair of the grid in both precisions
     against the reference; prints one JSON line per solve and the table
     entry: the fastest pair within 5e-5."""
-    ref_s = _make_solver(w, mode, "fp64", stream, dev, *REF_TOL)
-    ref, ref_ms = _timed_solve(ref_s)
-    ref_s.close()
+    ref, ref_ms = reference_solve(w, mode, stream, dev)
     print(json.dumps({"reference": ref["dG"], "ms": ref_ms, "tol": REF_TOL,
                       "gmres": ref["gmres_iters"], "scf": ref["scf_iters"]}), flush=True)
     for precision in ("mixed", "fp64"):
@@ -249,6 +268,43 @@ def calibrate(w, mode, stream, dev, args):
                                              None if best is None else best[1:]), flush=True)
 
 
+def oracle_times(products):
+    """Time to solution of the FP64 CPU oracle on this host: full solves
+    (dense LU) of the 1280- and 5120-panel spheres, and for the larger
+    workloads the time of one matrix-free O(N^2) product times the number
+    of operator products the GPU solve of the same workload needed
+    (extrapolated).  `products`: workload -> GPU product count (None: a
+    product count is not available, report the product time only)."""
+    import numpy as np
+    from oracle import bie, solver as osolver
+    from synth import workload
+    out = {"cpu_model": _cpu_model(),
+           "threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))}
+    for name in ("sphere_1280", "sphere_5120"):
+        w = workload(name)
+        p = w["params"]
+        t0 = time.perf_counter()
+        sol = osolver.BemSolvent(w["verts"], w["tris"], p["eps_in"], p["eps_out"], p["kappa"])
+        r = osolver.solvation(w["xyz"], w["q"], w["d"], w["Q9"], w["alpha"], sol,
+                              tol_debye=p["scf_tol_debye"])
+        out[name] = {"solve_s": time.perf_counter() - t0, "kind": "measured",
+                     "scf_iters": r["scf_iters"], "dG": r["dG"]}
+        _progress("oracle", name, out[name])
+    for name, nprod in products.items():
+        w = workload(name)
+        m = bie.Mesh(w["verts"], w["tris"], w["params"]["kappa"])
+        x = np.random.default_rng(0).normal(size=2 * m.N)
+        rows = min(m.N, 2048)
+        t0 = time.perf_counter()
+        m.operator_sums(x[:m.N], x[m.N:], rows=(0, rows))
+        t_prod = (time.perf_counter() - t0) * m.N / rows
+        out[name] = {"product_s": t_prod, "kind": "extrapolated",
+                     "gpu_products": nprod,
+                     "solve_s": None if nprod is None else t_prod * nprod}
+        _progress("oracle", name, out[name])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,6 +323,10 @@ def main():
     ap.add_argument("--calibrate", action="store_true",
                     help="search the tolerance grid against the reference (prints the "
                          "SOLVE_TOL entries) instead of the benchmark")
+    ap.add_argument("--oracle-times", default=None,
+                    help="time the FP64 CPU oracle instead of the benchmark: full solves "
+                         "of the two small spheres and, per 'workload=gpu_products' item "
+                         "of this comma-separated list, one product extrapolated")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device-to-device copy first (the reference "
                          "dispatch for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -277,6 +337,14 @@ def main():
               "path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
+
+    if args.oracle_times is not None:
+        products = {}
+        for item in filter(None, args.oracle_times.split(",")):
+            name, _, n = item.partition("=")
+            products[name] = int(n) if n else None
+        print(json.dumps({"oracle_times": oracle_times(products)}), flush=True)
+        return
 
     import torch
     from synth import workload
@@ -307,16 +375,21 @@ def main():
     G = int(p["gauss_far"]) * N
     gtol, stol = tol_for(args.precision)
     s = _make_solver(w, mode, args.precision, stream, dev, gtol, stol)
+    _progress("workload", args.workload, "panels", N, "sites", len(w["q"]), "tolerances",
+              gtol, stol)
     for _ in range(args.warmup):
         s.solve(outputs=False)
+        _progress("warm-up solve done")
     s.kernel_stats(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     matvecs = 0
     res = None
-    for _ in range(args.steps):
+    for k in range(args.steps):
         res = s.solve(outputs=False)
         matvecs += res["matvecs"]
+        if k % 5 == 4:
+            _progress("timed solves done:", k + 1)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st = s.kernel_stats(False)
@@ -364,9 +437,8 @@ def main():
         s64.solve(outputs=False)  # first-solve set-up, as the warm-up of the timed steps
         r64, fp64_ms = _timed_solve(s64)
         s64.close()
-        sref = _make_solver(w, mode, "fp64", stream, dev, *REF_TOL)
-        ref, ref_ms = _timed_solve(sref)
-        sref.close()
+        _progress("fp64 solve done: %.0f ms; reference" % fp64_ms)
+        ref, ref_ms = reference_solve(w, mode, stream, dev)
         err = lambda r: abs(r["dG"] - ref["dG"]) / abs(ref["dG"])
         solve_cmp = {"mixed_ms": ms_per_step, "fp64_ms": fp64_ms,
                      "speedup_mixed_over_fp64": fp64_ms / ms_per_step,
@@ -380,6 +452,7 @@ def main():
 
     cpu = None
     if rank == 0 and not args.no_cpu_baseline:
+        _progress("cpu baseline")
         cpu = cpu_baseline(w, args.cpu_seconds)
         cpu["cpu_model"] = _cpu_model()
 

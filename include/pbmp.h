@@ -145,11 +145,19 @@ typedef struct pbmp_result {
  * no warm start. */
 void pbmp_default_options(pbmp_options *o);
 
-/* Create a context on the current HIP device.  Validates the options
- * (PBMP_EARG on a value out of range).  *out receives the context. */
+/* Create a context on the current HIP device for one dielectric problem of
+ * the method (section "The boundary integral formulation", eq. pde: eps_in
+ * inside the surface, eps_out and kappa outside) and its discretisation
+ * (section "The boundary element method": far and near rules; section
+ * "The treecode algorithm": theta, order, leaf size; GMRES and the
+ * self-consistent loop of section "Self-consistent induced field").
+ * Validates the options (PBMP_EARG on a value out of range, before any
+ * device call).  *out receives the context. */
 int pbmp_create(const pbmp_options *o, pbmp_ctx **out);
 
-/* Change the solver settings of an existing context between solves:
+/* Change the solver settings of an existing context between solves (the
+ * GMRES and self-consistent-loop settings of sections "The boundary element
+ * method" and "Self-consistent induced field", and the precision):
  * gmres_restart, gmres_tol, gmres_maxit, scf_tol_debye, scf_omega,
  * scf_maxit, warm_start and precision are taken from *o (range-checked as
  * in pbmp_create); every other field must equal the context's (PBMP_EARG
@@ -191,7 +199,9 @@ int pbmp_solve(pbmp_ctx *c, pbmp_result *r);
 /* One application of the boundary-integral operator (eq. integral_eq):
  * y = A x with x = [phi; dphi] in integral-equation normalisation
  * ([2nt], panel order of pbmp_set_mesh), y [2nt].  transpose != 0 applies
- * A^T (direct mode only).  Uses the context's mode and precision. */
+ * A^T: in direct mode the transposed entries, in treecode mode the exact
+ * transpose of the treecode product (the same lists and expansions).
+ * Uses the context's mode and precision. */
 int pbmp_matvec(pbmp_ctx *c, const double *x, double *y, int transpose,
                 int where);
 
@@ -205,7 +215,9 @@ int pbmp_rhs(pbmp_ctx *c, const double *p_total, double *f, int where);
  * phi, dphi/dx, dphi/dy, dphi/dz, xx, xy, xz, yy, yz, zz, physical units. */
 int pbmp_site_fields(pbmp_ctx *c, const double *x, double *out, int where);
 
-/* Gradient of dG_bar * dG with respect to site positions g_xyz [3m],
+/* Gradient of dG_bar * dG (eq. energy_multipole_polarizable, through the
+ * adjoint of eq. integral_eq and of the self-consistent loop) with respect
+ * to site positions g_xyz [3m],
  * charges g_q [m], dipoles g_d [3m], quadrupole entries g_Q9 [9m] (the nine
  * entries taken as independent, as they enter eq. rhs_multipole and eq.
  * energy_multipole_polarizable) and vertex positions g_verts [3nv], by the
@@ -220,10 +232,12 @@ int pbmp_site_fields(pbmp_ctx *c, const double *x, double *out, int where);
  * unchanged inputs (PBMP_ESTATE otherwise).  Any output may be NULL
  * (skipped).  In treecode mode the transposed solves use the exact
  * transpose of the treecode product, so site gradients are those of the
- * treecode energy; the operator's dependence on the vertices is
- * differentiated directly (O(nt^2)), so vertex gradients are those of the
- * direct operator at the treecode solution (agreement to the treecode's
- * accuracy).  Returns +1/+2 when an adjoint solve did not converge. */
+ * treecode energy, and the far-field operator entries are differentiated
+ * with the same lists and expansions (direct pairs; expansions
+ * differentiated in the target; local expansions differentiated in the
+ * source nodes), so vertex gradients are those of the treecode energy with
+ * the expansion centres held fixed, at the cost of a few products.
+ * Returns +1/+2 when an adjoint solve did not converge. */
 int pbmp_backward(pbmp_ctx *c, double dG_bar, double *g_xyz, double *g_q,
                   double *g_d, double *g_Q9, double *g_verts, int where);
 
@@ -279,6 +293,32 @@ int pbmp_tree_export(pbmp_ctx *c, int64_t counts[4], int32_t *perm, int32_t *box
                      int32_t *box_level, double *box_centre, double *box_radius,
                      int32_t *leaf_box, int32_t *m2p_ptr, int32_t *m2p_box,
                      int32_t *p2p_ptr, int32_t *p2p_box);
+
+/* Binding energies of a complex AB from three contexts solved with the
+ * same options: AB (the complex: receptor sites first, then the ligand's),
+ * the receptor A and the ligand B alone (section "Calculation of the
+ * binding energy").  out[0] = dG_solv(AB) - dG_solv(A) - dG_solv(B)
+ * (eq. rel_bind_energy); out[1] = G_AB - G_A - G_B with G the vacuum-state
+ * Coulomb energy of each solve (eq. bind_vac); out[2] = out[0] + out[1]
+ * (eq. bind_energy); kcal/mol, host memory.  PBMP_ESTATE unless each
+ * context holds a completed solve; errors are reported on `complex`. */
+int pbmp_binding_energies(pbmp_ctx *complex, pbmp_ctx *receptor, pbmp_ctx *ligand,
+                          double out[3]);
+
+/* Gradient of the relative binding energy with respect to a rigid
+ * translation t of the ligand, from the solved complex: sites
+ * [first_ligand_site, m) of the complex are the ligand's; a vertex of the
+ * complex surface belongs to the ligand when the site minimising
+ * |v - r_a| - R_a (radii [m], the sites' atomic radii, in `where` memory)
+ * is a ligand site; the ligand's own surface moves as a whole and the
+ * receptor does not move, so only the complex contributes:
+ *   g_t = sum over ligand sites of d dG_AB/dr + sum over ligand vertices of d dG_AB/dv,
+ * through a backward of the complex (pbmp_backward with dG_bar = 1; its
+ * tolerances and warnings).  g_t [3] (kcal/mol/A) and n_ligand_vertices
+ * (nullable) are host memory. */
+int pbmp_ligand_translation_gradient(pbmp_ctx *complex, int64_t first_ligand_site,
+                                     const double *radii, double g_t[3],
+                                     int64_t *n_ligand_vertices, int where);
 
 /* Message for the last failing call on c (never NULL). */
 const char *pbmp_last_error(const pbmp_ctx *c);

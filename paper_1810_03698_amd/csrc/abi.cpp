@@ -173,6 +173,31 @@ int pbmp_tree_export(pbmp_ctx *c, int64_t counts[4], int32_t *perm, int32_t *box
   });
 }
 
+int pbmp_binding_energies(pbmp_ctx *complex, pbmp_ctx *receptor, pbmp_ctx *ligand,
+                          double out[3]) {
+  if (!receptor || !ligand) return PBMP_EARG;
+  return guarded(complex, [&] {
+    PBMP_REQUIRE(out != nullptr, PBMP_EARG, "null output");
+    double ab, gab, a, ga, b, gb;
+    complex->rt->binding_terms(&ab, &gab);
+    receptor->rt->binding_terms(&a, &ga);
+    ligand->rt->binding_terms(&b, &gb);
+    out[0] = ab - a - b;
+    out[1] = gab - ga - gb;
+    out[2] = out[0] + out[1];
+    return 0;
+  });
+}
+
+int pbmp_ligand_translation_gradient(pbmp_ctx *complex, int64_t first_ligand_site,
+                                     const double *radii, double g_t[3],
+                                     int64_t *n_ligand_vertices, int where) {
+  return guarded(complex, [&] {
+    return complex->rt->ligand_translation_gradient(first_ligand_site, radii, where, g_t,
+                                                    n_ligand_vertices);
+  });
+}
+
 const char *pbmp_last_error(const pbmp_ctx *c) {
   if (!c) return g_create_error.c_str();
   return c->err.c_str();

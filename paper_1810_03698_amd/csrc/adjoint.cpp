@@ -57,7 +57,8 @@ void launch_mesh_adjoint(hipStream_t s, int N, int M, int nf, const double *src6
                          const int *tscol, const double *x, const double *lam,
                          const double *sigma, const double *xyz, const double *q,
                          const double *p, const double *Q, const double *Wp, double kappa,
-                         double eps_ratio, double *work, double *ge, double *out);
+                         double eps_ratio, double *work, double *ge, double *out, Tree *tree,
+                         double *part, double *partT);
 
 void Runtime::apply_transpose(const double *x, double *y, bool f64) {
   const bool use64 = f64 || fp64();
@@ -205,14 +206,16 @@ int Runtime::backward(double dGbar, double *g_xyz, double *g_q, double *g_d, dou
   if (g_verts) {
     // mesh: operator entries, right-hand side at the collocation points and
     // the readout, chained to the vertices
-    Dbuf<double> work, ge, pv;
+    Dbuf<double> work, ge, pv, partT;
     work.alloc(25 * (size_t)N);
     ge.alloc(12 * (size_t)std::max(nnz_, 1));
     pv.alloc(9 * (size_t)N);
+    Tree *tr = use_tree() ? tree_.get() : nullptr;
+    if (tr) partT.alloc(13 * (size_t)std::max(1, tr->max_slots_T) * N);
     launch_mesh_adjoint(s_, N, M, ru_.nf, src64_.p, geo_.p, verts_.p, tri_.p, ru_, nrow_.p,
                         ncol_.p, trow_.p, tent_.p, tsrow_.p, tscol_.p, x_.p, lx.p, sig.p,
                         sxyz_.p, sq_.p, p_.p, sQ_.p, Wp.p, o.kappa, o.eps_in / o.eps_out,
-                        work.p, ge.p, pv.p);
+                        work.p, ge.p, pv.p, tr, part_.p, partT.p);
     std::vector<double> hp(9 * (size_t)N);
     pv.download(hp.data(), hp.size(), s_);
     sync();

@@ -3,13 +3,15 @@
 // normals n_j, areas A_j, near-singular and singular integrals), the
 // right-hand side at the collocation points, and the readout at the sites.
 // Pair sums are accumulated into per-panel gradients with respect to
-// (c, y_q, n, A); near/self corrections are differentiated directly in the
-// vertices with dual numbers; a last kernel chains everything to the
-// vertices.  All FP64.
+// (c, y_q, n, A) -- the far-rule operator pairs directly here, or with the
+// treecode's lists and expansions (k_tree.hip) when the product uses them;
+// near/self corrections are differentiated directly in the vertices with
+// dual numbers; a last kernel chains everything to the vertices.  All FP64.
 #include <cmath>
 
 #include "dual.hpp"
 #include "kernels.hpp"
+#include "tree.hpp"
 #include "pair.hpp"
 #include "panel.hpp"
 
@@ -20,33 +22,6 @@ namespace {
 constexpr double kInv4Pi = 0.07957747154594767;
 constexpr int kB = 256;
 constexpr int kT = 64;
-
-// Far-rule pair function of the operator for R = c_i - y (one node):
-//   f = a1 n.R/r^3 - a2/r - a3 n.R (1 + k r) e/r^3 + a4 e/r,  e = e^{-k r}
-// with a1 = l1_i phi_j, a2 = l1_i dphi_j, a3 = l2_i phi_j, a4 = eps l2_i dphi_j
-// (the pair's share of lambda_x . A x).  Returns f, df/dR, df/dn.
-__device__ inline double op_pair(const double R[3], const double n[3], double kappa,
-                                 double a1, double a2, double a3, double a4, double gR[3],
-                                 double gn[3]) {
-  const double rr = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
-  if (rr < kMinR2d) {  // a node on the target (one-node rule, self panel): no term
-    for (int d = 0; d < 3; ++d) gR[d] = gn[d] = 0.0;
-    return 0.0;
-  }
-  const double r = sqrt(rr);
-  const double ri = 1.0 / r, ri3 = ri / rr, ri5 = ri3 / rr;
-  const double e = exp(-kappa * r);
-  const double nR = n[0] * R[0] + n[1] * R[1] + n[2] * R[2];
-  const double ky = (1.0 + kappa * r) * e;
-  const double f = a1 * nR * ri3 - a2 * ri - a3 * nR * ky * ri3 + a4 * e * ri;
-  const double c3 = e * (3.0 + 3.0 * kappa * r + kappa * kappa * rr);
-  for (int d = 0; d < 3; ++d) {
-    gR[d] = a1 * (n[d] * ri3 - 3.0 * nR * R[d] * ri5) + a2 * R[d] * ri3 -
-            a3 * (ky * n[d] * ri3 - nR * c3 * R[d] * ri5) - a4 * ky * R[d] * ri3;
-    gn[d] = a1 * R[d] * ri3 - a3 * ky * R[d] * ri3;
-  }
-  return f;
-}
 
 // per target panel i: d/dc_i of sum_j lambda_x . A x (far rule everywhere)
 __global__ __launch_bounds__(kB) void k_op_grad_target(int N, int nf,
@@ -368,16 +343,24 @@ void launch_mesh_adjoint(hipStream_t s, int N, int M, int nf, const double *src6
                          const int *tscol, const double *x, const double *lam,
                          const double *sigma, const double *xyz, const double *q,
                          const double *p, const double *Q, const double *Wp, double kappa,
-                         double eps_ratio, double *work, double *ge, double *out) {
+                         double eps_ratio, double *work, double *ge, double *out, Tree *tree,
+                         double *part, double *partT) {
   // work: gc[3N] gy[9N] gn[3N] gA[N] gv[9N]
   double *gc = work, *gy = gc + 3 * (size_t)N, *gn = gy + 9 * (size_t)N,
          *gA = gn + 3 * (size_t)N, *gv = gA + N;
   PBMP_HIP(hipMemsetAsync(work, 0, sizeof(double) * 25 * (size_t)N, s));
   const dim3 g1((N + kB - 1) / kB);
-  hipLaunchKernelGGL(k_op_grad_target, g1, dim3(kB), 0, s, N, nf, src64, geo, x, lam, kappa,
-                     eps_ratio, ru, gc);
-  hipLaunchKernelGGL(k_op_grad_source, g1, dim3(kB), 0, s, N, nf, src64, geo, x, lam, kappa,
-                     eps_ratio, ru, gy, gn, gA);
+  // far-rule operator entries: with the treecode's lists and expansions
+  // (the derivative of the treecode operator), else every pair directly
+  if (tree) {
+    tree_mesh_adjoint_far(*tree, s, nf, N, geo, src64, lam, kappa, eps_ratio, part, partT, gc,
+                          gy, gn, gA);
+  } else {
+    hipLaunchKernelGGL(k_op_grad_target, g1, dim3(kB), 0, s, N, nf, src64, geo, x, lam, kappa,
+                       eps_ratio, ru, gc);
+    hipLaunchKernelGGL(k_op_grad_source, g1, dim3(kB), 0, s, N, nf, src64, geo, x, lam, kappa,
+                       eps_ratio, ru, gy, gn, gA);
+  }
   hipLaunchKernelGGL(k_near_grad, dim3((N + 63) / 64), dim3(64), 0, s, N, rowptr, col, verts,
                      tri, geo, x, lam, kappa, eps_ratio, ru, ge);
   hipLaunchKernelGGL(k_near_grad_reduce, g1, dim3(kB), 0, s, N, rowptr, trow, tent, ge, gc,

@@ -38,12 +38,13 @@ template <int P> struct Multi {
   int e[n][3];
   int m1[n][3];
   int m2[n][3];
+  int p1[n][3];  // position of k + e_i (-1 beyond degree P)
   int deg[n];
   static constexpr int index(int i, int j, int l) {
     const int s = i + j + l;
     return s * (s + 1) * (s + 2) / 6 + (s - i) * (s - i + 1) / 2 + (s - i - j);
   }
-  constexpr Multi() : e(), m1(), m2(), deg() {
+  constexpr Multi() : e(), m1(), m2(), p1(), deg() {
     int k = 0;
     for (int s = 0; s <= P; ++s)
       for (int i = s; i >= 0; --i)
@@ -60,6 +61,8 @@ template <int P> struct Multi {
             m1[k][d] = (a[d] >= 0) ? index(a[0], a[1], a[2]) : -1;
             a[d] -= 1;
             m2[k][d] = (a[d] >= 0) ? index(a[0], a[1], a[2]) : -1;
+            a[d] += 3;
+            p1[k][d] = (s < P) ? index(a[0], a[1], a[2]) : -1;
           }
           ++k;
         }
@@ -638,61 +641,71 @@ __global__ __launch_bounds__(64) void k_m2p_tasks(int ntask, const int *__restri
   }
 }
 
-__global__ void k_finish_slots(int N, const int *__restrict__ tslots,
-                               const double *__restrict__ part,
-                               const int *__restrict__ rowptr, const int *__restrict__ col,
-                               const double *__restrict__ val, const double *__restrict__ x,
-                               double eps_ratio, double *__restrict__ y) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+// y = A x from the far-field slots and the near/self corrections.  A block
+// takes 256 consecutive rows (one thread per row): the slot sums are read
+// row-parallel (consecutive threads, consecutive addresses), and the rows'
+// correction entries, which form one contiguous run of the CSR arrays, are
+// staged through LDS in chunks with 16-byte coalesced loads, each thread
+// then walking its own row's entries in order (one thread per row reading
+// its row straight from memory touches a separate cache line per lane).
+constexpr int kFinRows = 256;
+constexpr int kFinChunk = 1024;  // entries per staging round (32 KB values, 4 KB columns)
+
+__global__ __launch_bounds__(kFinRows) void k_finish_slots(
+    int N, const int *__restrict__ tslots, const double *__restrict__ part,
+    const int *__restrict__ rowptr, const int *__restrict__ col,
+    const double *__restrict__ val, const double *__restrict__ x, double eps_ratio,
+    double *__restrict__ y) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  __shared__ __align__(16) double sval[4 * kFinChunk];
+  __shared__ int scol[kFinChunk];
+  const int i0 = blockIdx.x * kFinRows;
+  const int i = i0 + (int)threadIdx.x;
+  const bool live = i < N;
   double S[4] = {0.0, 0.0, 0.0, 0.0};
-  const int ns = tslots[i];
-  // slots in order, four at a time: the loads of four slots are issued
-  // before the first add (the kernel is bound by their latency)
-  int c = 0;
-  for (; c + 4 <= ns; c += 4) {
-    double v[4][4];
+  if (live) {
+    const int ns = tslots[i];
+    // slots in order, four at a time: the loads of four slots are issued
+    // before the first add
+    int c = 0;
+    for (; c + 4 <= ns; c += 4) {
+      double v[4][4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) v[u][k] = part[((size_t)(c + u) * 4 + k) * N + i];
+        for (int k = 0; k < 4; ++k) v[u][k] = part[((size_t)(c + u) * 4 + k) * N + i];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) S[k] += v[u][k];
-  }
-  for (; c < ns; ++c)
-    for (int k = 0; k < 4; ++k) S[k] += part[((size_t)c * 4 + k) * N + i];
-  const int e0 = rowptr[i], e1 = rowptr[i + 1];
-  int e = e0;
-  for (; e + 4 <= e1; e += 4) {
-    int jj[4];
-    double vv[4][4], ph[4], dp[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) jj[u] = col[e + u];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      ph[u] = x[jj[u]];
-      dp[u] = x[N + jj[u]];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) vv[u][k] = val[4 * (size_t)(e + u) + k];
+        for (int k = 0; k < 4; ++k) S[k] += v[u][k];
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      S[0] += vv[u][0] * dp[u];
-      S[1] += vv[u][1] * ph[u];
-      S[2] += vv[u][2] * dp[u];
-      S[3] += vv[u][3] * ph[u];
+    for (; c < ns; ++c)
+      for (int k = 0; k < 4; ++k) S[k] += part[((size_t)c * 4 + k) * N + i];
+  }
+  const int eb = rowptr[i0], ee = rowptr[min(i0 + kFinRows, N)];
+  const int my0 = live ? rowptr[i] : ee, my1 = live ? rowptr[i + 1] : ee;
+  for (int c0 = eb; c0 < ee; c0 += kFinChunk) {
+    const int n = min(kFinChunk, ee - c0);
+    __syncthreads();
+    {
+      const d2 *g = reinterpret_cast<const d2 *>(val + 4 * (size_t)c0);
+      d2 *d = reinterpret_cast<d2 *>(sval);
+      for (int e = threadIdx.x; e < 2 * n; e += kFinRows) d[e] = g[e];
+      for (int e = threadIdx.x; e < n; e += kFinRows) scol[e] = col[c0 + e];
+    }
+    __syncthreads();
+    const int a = max(my0, c0) - c0, b = min(my1, c0 + n) - c0;
+    for (int e = a; e < b; ++e) {
+      const int j = scol[e];
+      const double ph = x[j], dp = x[N + j];
+      const double *v = sval + 4 * e;
+      S[0] += v[0] * dp;
+      S[1] += v[1] * ph;
+      S[2] += v[2] * dp;
+      S[3] += v[3] * ph;
     }
   }
-  for (; e < e1; ++e) {
-    const int j = col[e];
-    const double ph = x[j], dp = x[N + j];
-    S[0] += val[4 * (size_t)e] * dp;
-    S[1] += val[4 * (size_t)e + 1] * ph;
-    S[2] += val[4 * (size_t)e + 2] * dp;
-    S[3] += val[4 * (size_t)e + 3] * ph;
-  }
+  if (!live) return;
   const double ph = x[i];
   y[i] = 0.5 * ph + S[1] - S[0];
   y[N + i] = 0.5 * ph - S[3] + eps_ratio * S[2];
@@ -1138,6 +1151,412 @@ void tree_T_far_p(Tree &t, hipStream_t s, int nf, int N, const double *geo,
   }
 }
 
+
+// ======================================================= mesh adjoint
+// Far-field part of the gradient of lambda . A x with respect to the
+// collocation points c_i (target side) and to the far nodes y_g, normals n_j
+// and areas A_j (source side), with the same octree, lists and expansions
+// as the treecode product, so that the vertex gradient costs what a
+// product costs.  Per target i the form is
+//   l1_i (S_KL - S_VL) + l2_i (eps S_VY - S_KY)
+// (the strengths s_V, s_K of the forward solution packed in the records).
+// Exact derivatives of the discrete treecode operator with the expansion
+// centres held fixed: direct pairs through op_pair; an accepted box's
+// expansion, differentiated in the target, d/dx_i a_k(x - c) =
+// -(k_i + 1) a_{k + e_i} (coefficients to degree P + 2); in the sources, the
+// local expansions L_k = sum_i lambda_i a_k(x_i - c) of every box on a
+// leaf's path (as in the transposed product) differentiated in the node
+// h = y - c: the node's share of the form is
+//   s_K n.grad_h P_K(h) + s_V P_V(h),
+//   P_K = sum_{|k|<=P+1} (L^L_k - L^Y_k) h^k,  P_V = sum_{|k|<=P} (eps L^Y_k - L^L_k) h^k,
+// with gradients in h, in n and in the area (the strengths are linear in A).
+
+// target side, direct pairs: per forward P2P task, g_i = d/dc_i of the form
+// over the task's source panels; partial slots [slot][4][N] (components 0..2)
+template <int NF>
+__global__ __launch_bounds__(64) void k_p2p_grad_tasks(int ntask, const int *__restrict__ tasks,
+                                                       const int *__restrict__ slots,
+                                                       const int *__restrict__ ranges,
+                                                       const double *__restrict__ src64,
+                                                       const double *__restrict__ geo,
+                                                       const double *__restrict__ lam, int N,
+                                                       double kappa, double eps_ratio,
+                                                       double *__restrict__ part) {
+  constexpr int kTileG = 64;
+  __shared__ __align__(16) double sh[kTileG * 16];
+  const int task = xcd_task(ntask);
+  if (task < 0) return;
+  const int t0 = tasks[4 * task], t1 = tasks[4 * task + 1];
+  const int lb = tasks[4 * task + 2], le = tasks[4 * task + 3];
+  const int slot = slots[task];
+  const int lane = (int)threadIdx.x;
+  for (int tb = t0; tb < t1; tb += 64) {
+    const int t = tb + lane, tl = min(t, t1 - 1);
+    const double c[3] = {geo[tl], geo[N + tl], geo[2 * N + tl]};
+    const double l1 = lam[tl], l2 = eps_ratio * lam[N + tl], l2k = lam[N + tl];
+    double g[3] = {0.0, 0.0, 0.0};
+    for (int l = lb; l < le; ++l) {
+      const int s0 = ranges[2 * l], s1 = ranges[2 * l + 1];
+      for (int jt = s0; jt < s1; jt += kTileG) {
+        const int nj = min(kTileG, s1 - jt);
+        __syncthreads();
+        stage_records<double, kTileG>(src64 + (size_t)jt * 16, sh, nj, lane);
+        __syncthreads();
+        for (int jj = 0; jj < nj; ++jj) {
+          const double *r = sh + 16 * jj;
+#pragma unroll
+          for (int q = 0; q < NF; ++q) {
+            const double R[3] = {c[0] - r[3 * q], c[1] - r[3 * q + 1], c[2] - r[3 * q + 2]};
+            double gR[3], gn[3];
+            op_pair(R, r + 9, kappa, l1 * r[14], l1 * r[13], l2k * r[14], l2 * r[13], gR, gn);
+            for (int d = 0; d < 3; ++d) g[d] += gR[d];
+          }
+        }
+      }
+    }
+    if (t < t1)
+      for (int d = 0; d < 3; ++d) part[((size_t)slot * 4 + d) * N + t] = g[d];
+  }
+}
+
+// target side, expansions: per forward M2P task (FP64 moments),
+// d/dx of sum_k a_k m_k = - sum_k (k_d + 1) a_{k + e_d} m_k
+template <int P>
+__global__ __launch_bounds__(64) void k_m2p_grad_tasks(int ntask, const int *__restrict__ tasks,
+                                                       const int *__restrict__ slots,
+                                                       const int *__restrict__ boxes,
+                                                       const double *__restrict__ center,
+                                                       const double *__restrict__ mom,
+                                                       const double *__restrict__ geo,
+                                                       const double *__restrict__ lam, int N,
+                                                       double kappa, double eps_ratio,
+                                                       double *__restrict__ part) {
+  constexpr Multi<P + 2> mi{};
+  constexpr int NC = Orders<P>::NV, NK = Orders<P>::NK, NM = Orders<P>::NM;
+  constexpr int NG = Multi<P + 2>::n;
+  __shared__ double smom[kM2PChunkBoxes * NM];
+  __shared__ double scen[kM2PChunkBoxes * 3];
+  __shared__ int sbox[kM2PChunkBoxes];
+  const int task = xcd_task(ntask);
+  if (task < 0) return;
+  const int t0 = tasks[4 * task], t1 = tasks[4 * task + 1];
+  const int lb = tasks[4 * task + 2], le = tasks[4 * task + 3];
+  const int slot = slots[task];
+  const int nb = le - lb;
+  if (threadIdx.x < nb) sbox[threadIdx.x] = boxes[lb + threadIdx.x];
+  __syncthreads();
+  for (int e = threadIdx.x; e < nb * NM; e += 64) smom[e] = mom[(size_t)sbox[e / NM] * NM + e % NM];
+  for (int e = threadIdx.x; e < nb * 3; e += 64) scen[e] = center[3 * sbox[e / 3] + e % 3];
+  __syncthreads();
+  for (int tb = t0; tb < t1; tb += 64) {
+    const int t = tb + (int)threadIdx.x, tl = min(t, t1 - 1);
+    const double x[3] = {geo[tl], geo[N + tl], geo[2 * N + tl]};
+    const double l1 = lam[tl], l2 = lam[N + tl];
+    double g[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < nb; ++b) {
+      const double D[3] = {x[0] - scen[3 * b], x[1] - scen[3 * b + 1], x[2] - scen[3 * b + 2]};
+      const double R2 = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
+      const double ri = rsqrt_fp64(R2), iR2 = ri * ri;
+      const double ek = exp_fp64(-kappa * R2 * ri);
+      double a[NG], ay[NG], by[NG];
+      a[0] = ri;
+      by[0] = ek;
+      ay[0] = ek * ri;
+#pragma unroll
+      for (int k = 1; k < NG; ++k) {
+        const int sd = mi.deg[k];
+        double S1 = 0, S2 = 0, Y1 = 0, Y2 = 0, B1 = 0, B2 = 0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          if (mi.m1[k][d] >= 0) {
+            S1 += D[d] * a[mi.m1[k][d]];
+            Y1 += D[d] * ay[mi.m1[k][d]];
+            B1 += D[d] * by[mi.m1[k][d]];
+          }
+          if (mi.m2[k][d] >= 0) {
+            S2 += a[mi.m2[k][d]];
+            Y2 += ay[mi.m2[k][d]];
+            B2 += by[mi.m2[k][d]];
+          }
+        }
+        const double c1 = double(2 * sd - 1) / sd, c2 = double(sd - 1) / sd, ks = kappa / sd;
+        a[k] = (c1 * S1 - c2 * S2) * iR2;
+        by[k] = ks * (Y1 - Y2);
+        ay[k] = (c1 * Y1 - c2 * Y2 + ks * (B1 - B2)) * iR2;
+      }
+      const double *m = smom + b * NM;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double vl = 0, kl = 0, vy = 0, ky = 0;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+          const int kp = mi.p1[k][d];
+          const double w = -double(mi.e[k][d] + 1);
+          if (k < NC) {
+            vl += w * a[kp] * m[k];
+            vy += w * ay[kp] * m[k];
+          }
+          kl += w * a[kp] * m[NC + k];
+          ky += w * ay[kp] * m[NC + k];
+        }
+        g[d] += l1 * (kl - vl) + l2 * (eps_ratio * vy - ky);
+      }
+    }
+    if (t < t1)
+      for (int d = 0; d < 3; ++d) part[((size_t)slot * 4 + d) * N + t] = g[d];
+  }
+}
+
+// gc_i = sum of the target's forward slots
+__global__ void k_grad_slots_reduce(int N, int ncomp, int stride, const int *__restrict__ nslots,
+                                    int extra, const double *__restrict__ part,
+                                    double *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int ns = nslots[i] + extra;
+  for (int c = 0; c < ncomp; ++c) {
+    double v = 0.0;
+    for (int sl = 0; sl < ns; ++sl) v += part[((size_t)sl * stride + c) * N + i];
+    out[(size_t)ncomp * i + c] = v;
+  }
+}
+
+// gy (3 per node), gn, gA of a panel = sum of its transposed slots
+__global__ void k_grad_src_reduce(int N, const int *__restrict__ nslots,
+                                  const double *__restrict__ part, double *__restrict__ gy,
+                                  double *__restrict__ gn, double *__restrict__ gA) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const int ns = nslots[j];
+  double v[13];
+  for (int c = 0; c < 13; ++c) v[c] = 0.0;
+  for (int sl = 0; sl < ns; ++sl)
+    for (int c = 0; c < 13; ++c) v[c] += part[((size_t)sl * 13 + c) * N + j];
+  for (int c = 0; c < 9; ++c) gy[9 * (size_t)j + c] = v[c];
+  for (int c = 0; c < 3; ++c) gn[3 * (size_t)j + c] = v[9 + c];
+  gA[j] = v[12];
+}
+
+// source side, direct pairs: per P2P^T task (sources of one leaf on the
+// lanes, the task's targets through LDS), per source panel the 13 values
+// d/dy_q (3 per node), d/dn (3), d/dA (1); slots [slot][13][N]
+constexpr int kGradT = 13;
+
+template <int NF>
+__global__ __launch_bounds__(64) void k_p2pT_grad_tasks(int ntask, const int *__restrict__ tasks,
+                                                        const int *__restrict__ range,
+                                                        const int *__restrict__ subs,
+                                                        const double *__restrict__ src64,
+                                                        const double *__restrict__ geo,
+                                                        const double *__restrict__ lam, int N,
+                                                        double kappa, double eps_ratio,
+                                                        double *__restrict__ part) {
+  __shared__ double sh[64 * 5];
+  const int task = xcd_task(ntask);
+  if (task < 0) return;
+  const int B = tasks[4 * task], lb = tasks[4 * task + 1], le = tasks[4 * task + 2];
+  const int slot = tasks[4 * task + 3];
+  const int s0 = range[2 * B], s1 = range[2 * B + 1];
+  const int lane = (int)threadIdx.x;
+  for (int sb = s0; sb < s1; sb += 64) {
+    const int j = sb + lane, jl = min(j, s1 - 1);
+    double rec[15];
+    for (int c = 0; c < 15; ++c) rec[c] = src64[16 * (size_t)jl + c];
+    double acc[kGradT];
+    for (int c = 0; c < kGradT; ++c) acc[c] = 0.0;
+    for (int l = lb; l < le; ++l) {
+      const int a0 = subs[2 * l], a1 = subs[2 * l + 1];
+      for (int it = a0; it < a1; it += 64) {
+        const int nt = min(64, a1 - it);
+        __syncthreads();
+        if (lane < nt) {
+          const int i = it + lane;
+          sh[5 * lane] = geo[i];
+          sh[5 * lane + 1] = geo[N + i];
+          sh[5 * lane + 2] = geo[2 * N + i];
+          sh[5 * lane + 3] = lam[i];
+          sh[5 * lane + 4] = lam[N + i];
+        }
+        __syncthreads();
+        for (int e = 0; e < nt; ++e) {
+          const double *r = sh + 5 * e;
+#pragma unroll
+          for (int q = 0; q < NF; ++q) {
+            const double R[3] = {r[0] - rec[3 * q], r[1] - rec[3 * q + 1], r[2] - rec[3 * q + 2]};
+            double gR[3], gn[3];
+            const double f = op_pair(R, rec + 9, kappa, r[3] * rec[14], r[3] * rec[13],
+                                     r[4] * rec[14], eps_ratio * r[4] * rec[13], gR, gn);
+            for (int d = 0; d < 3; ++d) {
+              acc[3 * q + d] -= gR[d];
+              acc[9 + d] += gn[d];
+            }
+            acc[12] += f;
+          }
+        }
+      }
+    }
+    if (j < s1) {
+      const double iA = 1.0 / geo[6 * (size_t)N + j];
+      acc[12] *= iA;
+      for (int c = 0; c < kGradT; ++c) part[((size_t)slot * kGradT + c) * N + j] = acc[c];
+    }
+  }
+}
+
+// source side, expansions: at every node the local expansions of the
+// boxes on its leaf's path to the root (FP64 L from the M2P^T kernels with
+// z = lambda); slot tslotsT[j] - 1
+template <int P, int NF>
+__global__ __launch_bounds__(64) void k_l2p_grad(const int *__restrict__ leaves,
+                                                 const int *__restrict__ range,
+                                                 const int *__restrict__ parent,
+                                                 const int *__restrict__ ntask,
+                                                 const double *__restrict__ center,
+                                                 const double *__restrict__ Lb,
+                                                 const double *__restrict__ src64,
+                                                 const double *__restrict__ geo,
+                                                 const int *__restrict__ tslotsT, int N,
+                                                 double eps_ratio, double *__restrict__ part) {
+  constexpr Multi<P> mi{};
+  constexpr Multi<P + 1> miK{};
+  constexpr int NC = Orders<P>::NV, NK = Orders<P>::NK;
+  __shared__ double lp[kMaxChain][2 * NK];
+  __shared__ double lc[kMaxChain][3];
+  __shared__ int chain[kMaxChain];
+  __shared__ int nchain;
+  const int B = leaves[blockIdx.x];
+  if (threadIdx.x == 0) {
+    int n = 0;
+    for (int a = B; a >= 0 && n < kMaxChain; a = parent[a])
+      if (ntask[2 * a + 1] > 0) chain[n++] = a;
+    nchain = n;
+  }
+  __syncthreads();
+  const int nc = nchain;
+  for (int e = threadIdx.x; e < nc * 2 * NK; e += 64) {
+    const int a = e / (2 * NK), k = e % (2 * NK);
+    lp[a][k] = Lb[(size_t)chain[a] * 2 * NK + k];
+  }
+  for (int e = threadIdx.x; e < nc * 3; e += 64) lc[e / 3][e % 3] = center[3 * chain[e / 3] + e % 3];
+  __syncthreads();
+  for (int j = range[2 * B] + (int)threadIdx.x; j < range[2 * B + 1]; j += 64) {
+    const double *r = src64 + 16 * (size_t)j;
+    const double n[3] = {r[9], r[10], r[11]};
+    const double sv = r[13], sk = r[14];
+    double acc[kGradT];
+    for (int c = 0; c < kGradT; ++c) acc[c] = 0.0;
+    for (int a = 0; a < nc; ++a) {
+      for (int q = 0; q < NF; ++q) {
+        const double h[3] = {r[3 * q] - lc[a][0], r[3 * q + 1] - lc[a][1], r[3 * q + 2] - lc[a][2]};
+        double mono[NC];
+        mono[0] = 1.0;
+#pragma unroll
+        for (int k = 1; k < NC; ++k) {
+          const int d = mi.e[k][0] ? 0 : (mi.e[k][1] ? 1 : 2);
+          mono[k] = mono[mi.m1[k][d]] * h[d];
+        }
+        double pv = 0.0, gv[3] = {0, 0, 0}, gk[3] = {0, 0, 0};
+        double hk[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+          const double cK = lp[a][k] - lp[a][NK + k];
+          if (k < NC) {
+            const double cV = eps_ratio * lp[a][NK + k] - lp[a][k];
+            pv += cV * mono[k];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+              if (mi.m1[k][d] >= 0) gv[d] += cV * mi.e[k][d] * mono[mi.m1[k][d]];
+          }
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const int k1 = miK.m1[k][d];
+            if (k1 < 0) continue;
+            gk[d] += cK * miK.e[k][d] * mono[k1];
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+              const int k2 = miK.m1[k1][e];
+              if (k2 < 0) continue;
+              hk[d][e] += cK * miK.e[k][d] * miK.e[k1][e] * mono[k2];
+            }
+          }
+        }
+        const double qk = n[0] * gk[0] + n[1] * gk[1] + n[2] * gk[2];
+        for (int e = 0; e < 3; ++e) {
+          const double hn = n[0] * hk[0][e] + n[1] * hk[1][e] + n[2] * hk[2][e];
+          acc[3 * q + e] += sk * hn + sv * gv[e];
+          acc[9 + e] += sk * gk[e];
+        }
+        acc[12] += sk * qk + sv * pv;
+      }
+    }
+    const double iA = 1.0 / geo[6 * (size_t)N + j];
+    acc[12] *= iA;
+    const int slot = tslotsT[j] - 1;
+    for (int c = 0; c < kGradT; ++c) part[((size_t)slot * kGradT + c) * N + j] = acc[c];
+  }
+}
+
+template <int P>
+void tree_mesh_adjoint_far_p(Tree &t, hipStream_t s, int nf, int N, const double *geo,
+                             const double *src64, const double *lam, double kappa,
+                             double eps_ratio, double *part, double *partT, double *gc,
+                             double *gy, double *gn, double *gA) {
+  constexpr int NK = Orders<P>::NK;
+  // target side: direct pairs and expansions into the forward slots
+  const int nbp = ((t.n_p2p_tasks + 7) / 8) * 8;
+  if (nf == 3)
+    hipLaunchKernelGGL(k_p2p_grad_tasks<3>, dim3(nbp), dim3(64), 0, s, t.n_p2p_tasks,
+                       t.d_p2p_task.p, t.d_p2p_slot.p, t.d_p2p_src.p, src64, geo, lam, N,
+                       kappa, eps_ratio, part);
+  else
+    hipLaunchKernelGGL(k_p2p_grad_tasks<1>, dim3(nbp), dim3(64), 0, s, t.n_p2p_tasks,
+                       t.d_p2p_task.p, t.d_p2p_slot.p, t.d_p2p_src.p, src64, geo, lam, N,
+                       kappa, eps_ratio, part);
+  if (t.n_m2p_tasks > 0 && t.n_m2p_entries > 0) {
+    const int nbm = ((t.n_m2p_tasks + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_m2p_grad_tasks<P>), dim3(nbm), dim3(64), 0, s, t.n_m2p_tasks,
+                       t.d_m2p_task.p, t.d_m2p_slot.p, t.d_m2p_box.p, t.d_center.p,
+                       t.d_mom64.p, geo, lam, N, kappa, eps_ratio, part);
+  }
+  hipLaunchKernelGGL(k_grad_slots_reduce, dim3((N + 255) / 256), dim3(256), 0, s, N, 3, 4,
+                     t.d_tslots.p, 0, part, gc);
+  // source side: transposed direct pairs, local expansions at the nodes
+  const int nbt = ((t.n_p2pT_tasks + 7) / 8) * 8;
+  if (nf == 3)
+    hipLaunchKernelGGL(k_p2pT_grad_tasks<3>, dim3(nbt), dim3(64), 0, s, t.n_p2pT_tasks,
+                       t.d_p2pT_task.p, t.d_range.p, t.d_p2pT_sub.p, src64, geo, lam, N,
+                       kappa, eps_ratio, partT);
+  else
+    hipLaunchKernelGGL(k_p2pT_grad_tasks<1>, dim3(nbt), dim3(64), 0, s, t.n_p2pT_tasks,
+                       t.d_p2pT_task.p, t.d_range.p, t.d_p2pT_sub.p, src64, geo, lam, N,
+                       kappa, eps_ratio, partT);
+  t.d_Lpart.reserve((size_t)std::max(1, t.n_m2pT_tasks) * 2 * NK);
+  t.d_L.reserve((size_t)t.nbox * 2 * NK);
+  if (t.n_m2pT_tasks > 0) {
+    const int nbm = ((t.n_m2pT_tasks + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_m2pT_tasks<double, P, false>), dim3(nbm), dim3(64), 0, s,
+                       t.n_m2pT_tasks, t.d_m2pT_task.p, t.d_m2pT_sub.p, t.d_center.p, geo, lam,
+                       N, kappa, 0.0, t.d_Lpart.p);
+    hipLaunchKernelGGL((k_m2pT_tasks<double, P, true>), dim3(nbm), dim3(64), 0, s,
+                       t.n_m2pT_tasks, t.d_m2pT_task.p, t.d_m2pT_sub.p, t.d_center.p, geo, lam,
+                       N, kappa, 0.0, t.d_Lpart.p);
+  }
+  const int nl = t.nbox * 2 * NK;
+  hipLaunchKernelGGL(k_l_reduce, dim3((nl + 255) / 256), dim3(256), 0, s, t.nbox, 2 * NK,
+                     t.d_m2pT_count.p, t.d_m2pT_off.p, t.d_Lpart.p, t.d_L.p);
+  if (nf == 3)
+    hipLaunchKernelGGL((k_l2p_grad<P, 3>), dim3(t.nleaf), dim3(64), 0, s, t.d_leaves.p,
+                       t.d_range.p, t.d_parent.p, t.d_m2pT_count.p, t.d_center.p, t.d_L.p,
+                       src64, geo, t.d_tslotsT.p, N, eps_ratio, partT);
+  else
+    hipLaunchKernelGGL((k_l2p_grad<P, 1>), dim3(t.nleaf), dim3(64), 0, s, t.d_leaves.p,
+                       t.d_range.p, t.d_parent.p, t.d_m2pT_count.p, t.d_center.p, t.d_L.p,
+                       src64, geo, t.d_tslotsT.p, N, eps_ratio, partT);
+  hipLaunchKernelGGL(k_grad_src_reduce, dim3((N + 255) / 256), dim3(256), 0, s, N,
+                     t.d_tslotsT.p, partT, gy, gn, gA);
+  PBMP_HIP(hipGetLastError());
+}
+
 }  // namespace
 
 void tree_upload_exponents(Tree &t, hipStream_t s) {
@@ -1218,9 +1637,30 @@ void tree_apply(Tree &t, hipStream_t s, bool fp64, int nf, int N, const double *
 void launch_finish_slots(hipStream_t s, int N, const int *tslots, const double *part,
                          const int *rowptr, const int *col, const double *val,
                          const double *x, double eps_ratio, double *y) {
-  hipLaunchKernelGGL(k_finish_slots, dim3((N + 255) / 256), dim3(256), 0, s, N, tslots,
-                     part, rowptr, col, val, x, eps_ratio, y);
+  hipLaunchKernelGGL(k_finish_slots, dim3((N + kFinRows - 1) / kFinRows), dim3(kFinRows), 0, s,
+                     N, tslots, part, rowptr, col, val, x, eps_ratio, y);
   PBMP_HIP(hipGetLastError());
+}
+
+void tree_mesh_adjoint_far(Tree &t, hipStream_t s, int nf, int N, const double *geo,
+                           const double *src64, const double *lam, double kappa,
+                           double eps_ratio, double *part, double *partT, double *gc,
+                           double *gy, double *gn, double *gA) {
+  switch (t.prm.order) {
+#define PBMP_MA(P)                                                                          \
+  case P:                                                                                   \
+    tree_mesh_adjoint_far_p<P>(t, s, nf, N, geo, src64, lam, kappa, eps_ratio, part, partT, \
+                               gc, gy, gn, gA);                                             \
+    break;
+    PBMP_MA(1)
+    PBMP_MA(2)
+    PBMP_MA(3)
+    PBMP_MA(4)
+    PBMP_MA(5)
+    PBMP_MA(6)
+#undef PBMP_MA
+    default: throw Error(PBMP_EARG, "treecode order must be 1..6");
+  }
 }
 
 void tree_apply_transpose(Tree &t, hipStream_t s, bool fp64, int nf, int N, const double *geo,

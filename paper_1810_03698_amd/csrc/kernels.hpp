@@ -173,6 +173,14 @@ void tree_apply_transpose(Tree &t, hipStream_t s, bool fp64, int nf, int N, cons
                           const double *z, double kappa, double *part, const int *trow,
                           const int *tcol, const int *tent, const double *val, double eps_ratio,
                           double *y);
+// Far-field part of the mesh adjoint with the treecode: d/d(collocation
+// points) gc [3N] and d/d(far nodes, normals, areas) gy [9N], gn [3N],
+// gA [N] of lambda . A x (assigned, not accumulated); part: the product's
+// forward slots [max_slots][4][N], partT: [max_slots_T][13][N]
+void tree_mesh_adjoint_far(Tree &t, hipStream_t s, int nf, int N, const double *geo,
+                           const double *src64, const double *lam, double kappa,
+                           double eps_ratio, double *part, double *partT, double *gc,
+                           double *gy, double *gn, double *gA);
 void launch_finish_slots(hipStream_t s, int N, const int *tslots,
                          const double *part, const int *rowptr, const int *col,
                          const double *val, const double *x, double eps_ratio,

@@ -145,4 +145,33 @@ __device__ __forceinline__ void panel_terms(const T *rec, int nf, T px, T py,
   out[3] = nR * ky;
 }
 
+// Far-rule pair function of the operator for R = c_i - y (one node):
+//   f = a1 n.R/r^3 - a2/r - a3 n.R (1 + k r) e/r^3 + a4 e/r,  e = e^{-k r}
+// with a1 = l1_i phi_j, a2 = l1_i dphi_j, a3 = l2_i phi_j, a4 = eps l2_i dphi_j
+// (the pair's share of lambda_x . A x; with the panel's packed strengths
+// s_K, s_V in place of phi_j, dphi_j the weight and area are included).
+// Returns f, df/dR, df/dn.
+__device__ inline double op_pair(const double R[3], const double n[3], double kappa,
+                                 double a1, double a2, double a3, double a4, double gR[3],
+                                 double gn[3]) {
+  const double rr = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+  if (rr < kMinR2d) {  // a node on the target (one-node rule, self panel): no term
+    for (int d = 0; d < 3; ++d) gR[d] = gn[d] = 0.0;
+    return 0.0;
+  }
+  const double ri = rsqrt_fp64(rr);
+  const double r = rr * ri, ri3 = ri * ri * ri, ri5 = ri3 * ri * ri;
+  const double e = exp_fp64(-kappa * r);
+  const double nR = n[0] * R[0] + n[1] * R[1] + n[2] * R[2];
+  const double ky = (1.0 + kappa * r) * e;
+  const double f = a1 * nR * ri3 - a2 * ri - a3 * nR * ky * ri3 + a4 * e * ri;
+  const double c3 = e * (3.0 + 3.0 * kappa * r + kappa * kappa * rr);
+  for (int d = 0; d < 3; ++d) {
+    gR[d] = a1 * (n[d] * ri3 - 3.0 * nR * R[d] * ri5) + a2 * R[d] * ri3 -
+            a3 * (ky * n[d] * ri3 - nR * c3 * R[d] * ri5) - a4 * ky * R[d] * ri3;
+    gn[d] = a1 * R[d] * ri3 - a3 * ky * R[d] * ri3;
+  }
+  return f;
+}
+
 }  // namespace pbmp

@@ -944,6 +944,8 @@ int Runtime::solve(pbmp_result *r) {
   r->dG_pol_kcal = C * e[1];
   r->dG_kcal = C * (e[0] + e[1]);
   r->G_vac_kcal = C * (e[2] + e[3]);
+  last_dG_ = r->dG_kcal;
+  last_Gvac_ = r->G_vac_kcal;
   for (int c = 0; c < 3; ++c) {
     r->dipole_vac_debye[c] = debye_per_e_ang() * e[4 + c];
     r->dipole_diss_debye[c] = debye_per_e_ang() * e[7 + c];

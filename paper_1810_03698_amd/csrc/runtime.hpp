@@ -64,6 +64,12 @@ class Runtime {
   bool has_stern() const { return (bool)outer_; }
   int backward(double dGbar, double *g_xyz, double *g_q, double *g_d,
                double *g_Q, double *g_verts, int where);
+  // the last solve's solvation energy and vacuum Coulomb energy (binding.cpp)
+  void binding_terms(double *dG, double *G_vac) const;
+  // d dG / dt for a rigid translation t of the sites [first_ligand, m) and
+  // of the vertices those sites own (binding.cpp)
+  int ligand_translation_gradient(int64_t first_ligand, const double *radii, int where,
+                                  double g_t[3], int64_t *n_ligand_vertices);
 
   std::string err;
   KernelClock clock;
@@ -111,6 +117,7 @@ class Runtime {
   Dbuf<double> io_a_, io_b_;  // permutation staging
   Dbuf<double> vac_perm_, vac_ind_;  // vacuum-state potential data [10M]
   bool solved_ = false;
+  double last_dG_ = 0.0, last_Gvac_ = 0.0;  // of the last solve
   bool warm_ok_ = false;  // x_, mu_d_, mu_v_ hold a previous solve of this mesh and site count
   int gmres_iters_ = 0, matvecs_ = 0;
   double last_relres_ = 0.0;

@@ -65,7 +65,7 @@ SYMBOLS = ["pbmp_default_options", "pbmp_create", "pbmp_set_mesh",
            "pbmp_set_sites", "pbmp_solve", "pbmp_matvec", "pbmp_rhs",
            "pbmp_site_fields", "pbmp_backward", "pbmp_last_error",
            "pbmp_destroy", "pbmp_kernel_stats", "pbmp_tree_export", "pbmp_set_stern",
-           "pbmp_set_options"]
+           "pbmp_set_options", "pbmp_binding_energies", "pbmp_ligand_translation_gradient"]
 
 
 def _torch_runtime_first():
@@ -100,6 +100,8 @@ def load():
     lib.pbmp_matvec.argtypes = [P, P, P, I, I]
     lib.pbmp_rhs.argtypes = [P, P, P, I]
     lib.pbmp_site_fields.argtypes = [P, P, P, I]
+    lib.pbmp_binding_energies.argtypes = [P, P, P, P]
+    lib.pbmp_ligand_translation_gradient.argtypes = [P, L, P, P, P, I]
     lib.pbmp_backward.argtypes = [P, D, P, P, P, P, P, I]
     lib.pbmp_last_error.argtypes = [P]
     lib.pbmp_last_error.restype = ctypes.c_char_p
@@ -112,7 +114,8 @@ def load():
     for name in ("pbmp_create", "pbmp_set_mesh", "pbmp_set_sites", "pbmp_solve",
                  "pbmp_matvec", "pbmp_rhs", "pbmp_site_fields", "pbmp_backward",
                  "pbmp_kernel_stats", "pbmp_tree_export", "pbmp_set_stern",
-                 "pbmp_set_options"):
+                 "pbmp_set_options", "pbmp_binding_energies",
+                 "pbmp_ligand_translation_gradient"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -339,6 +342,17 @@ class Solver:
         g["status"] = rc
         return g
 
+    def ligand_translation_gradient(self, first_ligand_site, radii):
+        """pbmp_ligand_translation_gradient: (g_t [3], number of ligand
+        vertices, status)."""
+        r = _Arg(radii, np.float64, self.m)
+        g = np.empty(3)
+        nlv = np.zeros(1, dtype=np.int64)
+        rc = self._check(self.lib.pbmp_ligand_translation_gradient(
+            self.ctx, int(first_ligand_site), r.ptr, g.ctypes.data, nlv.ctypes.data,
+            _common_where([r])), allow_warn=True)
+        return g, int(nlv[0]), rc
+
     def kernel_stats(self, enable=None):
         """Device time per kernel class (HIP events).  enable=1 starts
         collection (and resets), 0 stops, None just reads."""
@@ -368,6 +382,18 @@ class Solver:
         out["m2p_box"] = out["m2p_box"][:nm]
         out["p2p_box"] = out["p2p_box"][:npp]
         return out
+
+
+def binding_energies(complex_solver, receptor_solver, ligand_solver):
+    """pbmp_binding_energies of three solved contexts: (ddG, dG_bind_vac,
+    dG_bind_diss) in kcal/mol."""
+    out = np.empty(3)
+    lib = complex_solver.lib
+    rc = lib.pbmp_binding_energies(complex_solver.ctx, receptor_solver.ctx, ligand_solver.ctx,
+                                   out.ctypes.data)
+    if rc != 0:
+        raise PbmpError(rc, lib.pbmp_last_error(complex_solver.ctx).decode())
+    return tuple(out)
 
 
 def _empty_like_torch(t, n=None):

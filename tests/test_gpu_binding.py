@@ -80,14 +80,23 @@ def test_binding_energies_match_oracle(triad):
     assert abs(got["dG_bind_diss"] - (ddG + vac)) < 2e-10 * scale
 
 
+def _vertex_owner(verts, xyz, radii, is_ligand):
+    """Test-side statement of which complex vertices move with the ligand:
+    those whose closest atom sphere (smallest |v - r_a| - R_a) is a ligand
+    atom."""
+    d = np.linalg.norm(verts[:, None, :] - xyz[None], axis=2) - radii[None]
+    return is_ligand[np.argmin(d, axis=1)]
+
+
 def test_binding_translation_gradient_fd(triad):
     from paper_1810_03698_amd import Solver
-    from paper_1810_03698_amd.binding import relative_binding, vertex_owner
+    from paper_1810_03698_amd.binding import relative_binding
     A, B, AB = triad
     nR = len(A["q"])
     got = relative_binding(AB, A, B, n_receptor=nR, grad=True, **OPTS)
     is_lig = np.arange(len(AB["q"])) >= nR
-    own = vertex_owner(AB["verts"], AB["xyz"], AB["radii"], is_lig)
+    own = _vertex_owner(AB["verts"], AB["xyz"], AB["radii"], is_lig)
+    assert got["ligand_vertices"] == int(own.sum())
 
     def dG_complex(t):
         v = AB["verts"].copy()

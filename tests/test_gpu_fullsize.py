@@ -398,3 +398,70 @@ def test_position_gradient_fd_per_atom_globule_5000(g5000, say):
 @long_only
 def test_multipole_gradients_fd_globule_5000(g5000, say):
     _multipole_check(g5000, say)
+
+
+@long_only
+def test_binding_triad_fullsize(say):
+    """The full binding triad (receptor 3000 atoms / ~90k panels, ligand
+    200 / ~8k, complex 3200 / ~96k; treecode theta 0.5, P 4): the relative
+    binding energy (eq. rel_bind_energy) in mixed precision against FP64
+    (relative 1e-4), and the derivative of the FP64 relative binding energy
+    with respect to a rigid translation of the ligand (treecode adjoint,
+    vertex terms with the treecode's lists and expansions) against central
+    differences of FP64 direct solves of the complex (h = 1e-3 A along
+    each axis: the octree would move with the ligand, so differences of
+    treecode solves jump at the treecode's truncation level; the difference
+    of direct solves is smooth), at the treecode's accuracy (1e-4 of the
+    gradient's norm)."""
+    from paper_1810_03698_amd import Solver
+    from paper_1810_03698_amd.binding import relative_binding
+    wA, wB, wAB = (workload(n) for n in ("binding_receptor", "binding_ligand",
+                                          "binding_complex"))
+    nR = int(wAB["n_receptor"])
+    p = wAB["params"]
+    base = dict(eps_in=p["eps_in"], eps_out=p["eps_out"], kappa=p["kappa"], mode="treecode",
+                theta=0.5, order_P=4, leaf_panels=300, gmres_restart=100, gmres_maxit=20000,
+                scf_maxit=500)
+    t0 = time.perf_counter()
+    res = {}
+    for precision, gtol, stol in (("mixed", 1e-8, 1e-8), ("fp64", 1e-10, 1e-9)):
+        res[precision] = relative_binding(wAB, wA, wB, n_receptor=nR,
+                                          grad=(precision == "fp64"), precision=precision,
+                                          gmres_tol=gtol, scf_tol_debye=stol, **base)
+        r = res[precision]
+        say(precision, "ddG", r["ddG"], "vac", r["dG_bind_vac"], "diss", r["dG_bind_diss"],
+            "dG AB/A/B", r["dG_complex"], r["dG_receptor"], r["dG_ligand"],
+            "%.0f s" % (time.perf_counter() - t0))
+    rel = abs(res["mixed"]["ddG"] - res["fp64"]["ddG"]) / abs(res["fp64"]["ddG"])
+    say("ddG mixed vs fp64", rel)
+    assert rel < 1e-4
+    g = res["fp64"]["grad_t"]
+    say("grad_t", g, "ligand vertices", res["fp64"]["ligand_vertices"])
+    is_lig = np.arange(len(wAB["q"])) >= nR
+    own = np.empty(len(wAB["verts"]), bool)
+    for a in range(0, len(wAB["verts"]), 2048):
+        dd = np.linalg.norm(wAB["verts"][a:a + 2048, None, :] - wAB["xyz"][None], axis=2)
+        own[a:a + 2048] = is_lig[np.argmin(dd - wAB["radii"][None], axis=1)]
+    assert res["fp64"]["ligand_vertices"] == int(own.sum())
+    s = Solver(precision="fp64", **dict(base, mode="direct", gmres_tol=1e-10,
+                                        scf_tol_debye=1e-9, warm_start=True))
+    h = 1e-3
+    fd = np.empty(3)
+    for a in range(3):
+        e = []
+        for sg in (1.0, -1.0):
+            v = wAB["verts"].copy()
+            v[own, a] += sg * h
+            x = wAB["xyz"].copy()
+            x[is_lig, a] += sg * h
+            s.set_mesh(v, wAB["tris"])
+            s.set_sites(x, wAB["q"], wAB["d"], wAB["Q9"], wAB["alpha"])
+            r = s.solve(outputs=False)
+            assert r["status"] == 0
+            e.append(r["dG"])
+            say("direct complex", a, sg, r["dG"], r["gmres_iters"], "%.0f s" % (time.perf_counter() - t0))
+        fd[a] = (e[0] - e[1]) / (2 * h)
+    s.close()
+    err = np.abs(g - fd).max() / np.linalg.norm(fd)
+    say("translation gradient: treecode adjoint", g, "direct FD", fd, "err/|fd|", err)
+    assert err < 1e-4
