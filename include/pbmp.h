@@ -215,6 +215,22 @@ int pbmp_rhs(pbmp_ctx *c, const double *p_total, double *f, int where);
  * phi, dphi/dx, dphi/dy, dphi/dz, xx, xy, xz, yy, yz, zz, physical units. */
 int pbmp_site_fields(pbmp_ctx *c, const double *x, double *out, int where);
 
+/* pbmp_site_fields for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same values, with no device allocation, no free and no
+ * allocating library call.  x [2nt] and out [10m] are device pointers (the
+ * caller's panel and site order, as pbmp_site_fields).  The work memory (x in
+ * the internal panel order and the readout's per-chunk partial sums,
+ * 8 (2 nt + 10 m nchunk) bytes) lives in one static device buffer of 32 MiB
+ * per GPU that the library holds until the process ends; its address is
+ * looked up when a context is created.  PBMP_EARG when 8 (2 nt + 10 m) bytes
+ * exceed 32 MiB (fewer partial-sum chunks are used when the full count does
+ * not fit); PBMP_ESTATE without mesh and sites or with a Stern layer.  Every
+ * call on one GPU uses the same buffer, which keeps the last call's
+ * contents (every value a call reads it writes first): calls that overlap
+ * on one GPU, from any contexts or threads, race. */
+int pbmp_site_fields_noalloc(pbmp_ctx *c, const double *x, double *out);
+
 /* Gradient of dG_bar * dG (eq. energy_multipole_polarizable, through the
  * adjoint of eq. integral_eq and of the self-consistent loop) with respect
  * to site positions g_xyz [3m],

@@ -114,6 +114,13 @@ int pbmp_site_fields(pbmp_ctx *c, const double *x, double *out, int where) {
   });
 }
 
+int pbmp_site_fields_noalloc(pbmp_ctx *c, const double *x, double *out) {
+  return guarded(c, [&] {
+    c->rt->site_fields_noalloc(x, out);
+    return 0;
+  });
+}
+
 int pbmp_backward(pbmp_ctx *c, double dG_bar, double *g_xyz, double *g_q,
                   double *g_d, double *g_Q9, double *g_verts, int where) {
   return guarded(c, [&] {

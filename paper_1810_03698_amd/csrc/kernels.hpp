@@ -80,6 +80,10 @@ void launch_readout(hipStream_t s, bool fp64, bool full, int N, int M,
 // Source chunks of the far readout for N panels and M sites (enough blocks
 // of 64 sites x one chunk to fill the device); part holds nchunk * M * 10.
 int readout_chunks(int N, int M);
+// static device scratch of the entry point that allocates nothing: its size
+// and its address on the current device (looked up once per device)
+size_t static_scratch_bytes();
+double *static_scratch();
 
 // Coulomb field of the permanent multipoles at the sites, excluding pairs of
 // the same polarisation group: Eperm[3M] = -grad phi_perm / eps_in.

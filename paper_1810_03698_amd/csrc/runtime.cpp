@@ -196,7 +196,10 @@ Runtime::Runtime(const pbmp_options &opt) : o(opt) {
   }
   ru_.ngl = 16;
   gauss_legendre(16, ru_.glx, ru_.glw);
-  // the first HIP call comes after the host-only set-up above
+  // the first HIP calls come after the host-only set-up above: the static
+  // scratch's device address is looked up now (once per device), so that
+  // the entry point using it makes no runtime set-up call itself
+  (void)static_scratch();
   if (o.hip_stream) {
     s_ = reinterpret_cast<hipStream_t>(o.hip_stream);
   } else {

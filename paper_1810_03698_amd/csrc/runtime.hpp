@@ -52,6 +52,9 @@ class Runtime {
   void matvec_user(const double *x, double *y, int transpose, int where);
   void rhs_user(const double *p, double *f, int where);
   void site_fields_user(const double *x, double *out, int where);
+  // site_fields_user with device pointers and its work memory in the static
+  // scratch (k_static.hip): no device allocation
+  void site_fields_noalloc(const double *x, double *out);
   void tree_export(int64_t counts[4], int32_t *perm, int32_t *box_range, int32_t *box_level,
                    double *box_centre, double *box_radius, int32_t *leaf_box,
                    int32_t *m2p_ptr, int32_t *m2p_box, int32_t *p2p_ptr,

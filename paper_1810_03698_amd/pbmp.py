@@ -65,7 +65,8 @@ SYMBOLS = ["pbmp_default_options", "pbmp_create", "pbmp_set_mesh",
            "pbmp_set_sites", "pbmp_solve", "pbmp_matvec", "pbmp_rhs",
            "pbmp_site_fields", "pbmp_backward", "pbmp_last_error",
            "pbmp_destroy", "pbmp_kernel_stats", "pbmp_tree_export", "pbmp_set_stern",
-           "pbmp_set_options", "pbmp_binding_energies", "pbmp_ligand_translation_gradient"]
+           "pbmp_set_options", "pbmp_site_fields_noalloc", "pbmp_binding_energies",
+           "pbmp_ligand_translation_gradient"]
 
 
 def _torch_runtime_first():
@@ -100,6 +101,7 @@ def load():
     lib.pbmp_matvec.argtypes = [P, P, P, I, I]
     lib.pbmp_rhs.argtypes = [P, P, P, I]
     lib.pbmp_site_fields.argtypes = [P, P, P, I]
+    lib.pbmp_site_fields_noalloc.argtypes = [P, P, P]
     lib.pbmp_binding_energies.argtypes = [P, P, P, P]
     lib.pbmp_ligand_translation_gradient.argtypes = [P, L, P, P, P, I]
     lib.pbmp_backward.argtypes = [P, D, P, P, P, P, P, I]
@@ -114,7 +116,7 @@ def load():
     for name in ("pbmp_create", "pbmp_set_mesh", "pbmp_set_sites", "pbmp_solve",
                  "pbmp_matvec", "pbmp_rhs", "pbmp_site_fields", "pbmp_backward",
                  "pbmp_kernel_stats", "pbmp_tree_export", "pbmp_set_stern",
-                 "pbmp_set_options", "pbmp_binding_energies",
+                 "pbmp_set_options", "pbmp_site_fields_noalloc", "pbmp_binding_energies",
                  "pbmp_ligand_translation_gradient"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -317,6 +319,16 @@ class Solver:
         o = _Arg(out, np.float64, 10 * self.m)
         self._check(self.lib.pbmp_site_fields(self.ctx, a.ptr, o.ptr,
                                               _common_where([a, o])))
+        return out
+
+    def site_fields_noalloc(self, x, out):
+        """pbmp_site_fields_noalloc: x [2 nt] and out [m, 10] are float64
+        torch tensors on the device; the library allocates nothing."""
+        a = _Arg(x, np.float64, 2 * self.nt)
+        o = _Arg(out, np.float64, 10 * self.m)
+        if a.where != DEVICE or o.where != DEVICE:
+            raise ValueError("site_fields_noalloc takes device tensors")
+        self._check(self.lib.pbmp_site_fields_noalloc(self.ctx, a.ptr, o.ptr))
         return out
 
     def backward(self, dG_bar=1.0, verts=True, device=None):
