@@ -641,71 +641,45 @@ __global__ __launch_bounds__(64) void k_m2p_tasks(int ntask, const int *__restri
   }
 }
 
-// y = A x from the far-field slots and the near/self corrections.  A block
-// takes 256 consecutive rows (one thread per row): the slot sums are read
-// row-parallel (consecutive threads, consecutive addresses), and the rows'
-// correction entries, which form one contiguous run of the CSR arrays, are
-// staged through LDS in chunks with 16-byte coalesced loads, each thread
-// then walking its own row's entries in order (one thread per row reading
-// its row straight from memory touches a separate cache line per lane).
-constexpr int kFinRows = 256;
-constexpr int kFinChunk = 1024;  // entries per staging round (32 KB values, 4 KB columns)
+// y = A x from the far-field slots and the near/self corrections.  Four
+// lanes per row (a wave takes 16 rows): lane u of a row sums the row's slots
+// u, u + 4, ... and its correction entries u, u + 4, ..., so that the
+// four lanes read neighbouring entries together and a launch holds four
+// times as many waves to hide the latency of the scattered reads of x;
+// the lanes' sums are then added in a fixed order (lane shuffles).
+constexpr int kFinLanes = 4;
+constexpr int kFinBlock = 256;
 
-__global__ __launch_bounds__(kFinRows) void k_finish_slots(
+__global__ __launch_bounds__(kFinBlock) void k_finish_slots(
     int N, const int *__restrict__ tslots, const double *__restrict__ part,
     const int *__restrict__ rowptr, const int *__restrict__ col,
     const double *__restrict__ val, const double *__restrict__ x, double eps_ratio,
     double *__restrict__ y) {
-  typedef double d2 __attribute__((ext_vector_type(2)));
-  __shared__ __align__(16) double sval[4 * kFinChunk];
-  __shared__ int scol[kFinChunk];
-  const int i0 = blockIdx.x * kFinRows;
-  const int i = i0 + (int)threadIdx.x;
+  const int t = blockIdx.x * kFinBlock + (int)threadIdx.x;
+  const int i = t / kFinLanes, u = t % kFinLanes;
   const bool live = i < N;
+  const int il = live ? i : N - 1;
   double S[4] = {0.0, 0.0, 0.0, 0.0};
-  if (live) {
-    const int ns = tslots[i];
-    // slots in order, four at a time: the loads of four slots are issued
-    // before the first add
-    int c = 0;
-    for (; c + 4 <= ns; c += 4) {
-      double v[4][4];
+  const int ns = tslots[il];
+  for (int c = u; c < ns; c += kFinLanes)
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) v[u][k] = part[((size_t)(c + u) * 4 + k) * N + i];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) S[k] += v[u][k];
-    }
-    for (; c < ns; ++c)
-      for (int k = 0; k < 4; ++k) S[k] += part[((size_t)c * 4 + k) * N + i];
+    for (int k = 0; k < 4; ++k) S[k] += part[((size_t)c * 4 + k) * N + il];
+  const int e1 = rowptr[il + 1];
+  for (int e = rowptr[il] + u; e < e1; e += kFinLanes) {
+    const int j = col[e];
+    const double ph = x[j], dp = x[N + j];
+    const double *v = val + 4 * (size_t)e;
+    S[0] += v[0] * dp;
+    S[1] += v[1] * ph;
+    S[2] += v[2] * dp;
+    S[3] += v[3] * ph;
   }
-  const int eb = rowptr[i0], ee = rowptr[min(i0 + kFinRows, N)];
-  const int my0 = live ? rowptr[i] : ee, my1 = live ? rowptr[i + 1] : ee;
-  for (int c0 = eb; c0 < ee; c0 += kFinChunk) {
-    const int n = min(kFinChunk, ee - c0);
-    __syncthreads();
-    {
-      const d2 *g = reinterpret_cast<const d2 *>(val + 4 * (size_t)c0);
-      d2 *d = reinterpret_cast<d2 *>(sval);
-      for (int e = threadIdx.x; e < 2 * n; e += kFinRows) d[e] = g[e];
-      for (int e = threadIdx.x; e < n; e += kFinRows) scol[e] = col[c0 + e];
-    }
-    __syncthreads();
-    const int a = max(my0, c0) - c0, b = min(my1, c0 + n) - c0;
-    for (int e = a; e < b; ++e) {
-      const int j = scol[e];
-      const double ph = x[j], dp = x[N + j];
-      const double *v = sval + 4 * e;
-      S[0] += v[0] * dp;
-      S[1] += v[1] * ph;
-      S[2] += v[2] * dp;
-      S[3] += v[3] * ph;
-    }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    S[k] += __shfl_xor(S[k], 1, kFinLanes);
+    S[k] += __shfl_xor(S[k], 2, kFinLanes);
   }
-  if (!live) return;
+  if (!live || u != 0) return;
   const double ph = x[i];
   y[i] = 0.5 * ph + S[1] - S[0];
   y[N + i] = 0.5 * ph - S[3] + eps_ratio * S[2];
@@ -1637,8 +1611,9 @@ void tree_apply(Tree &t, hipStream_t s, bool fp64, int nf, int N, const double *
 void launch_finish_slots(hipStream_t s, int N, const int *tslots, const double *part,
                          const int *rowptr, const int *col, const double *val,
                          const double *x, double eps_ratio, double *y) {
-  hipLaunchKernelGGL(k_finish_slots, dim3((N + kFinRows - 1) / kFinRows), dim3(kFinRows), 0, s,
-                     N, tslots, part, rowptr, col, val, x, eps_ratio, y);
+  const int rows_per_block = kFinBlock / kFinLanes;
+  hipLaunchKernelGGL(k_finish_slots, dim3((N + rows_per_block - 1) / rows_per_block),
+                     dim3(kFinBlock), 0, s, N, tslots, part, rowptr, col, val, x, eps_ratio, y);
   PBMP_HIP(hipGetLastError());
 }
 
