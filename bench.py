@@ -39,19 +39,21 @@ COPY_BYTES = 256 << 20
 # HBM traffic of the dominant kernel per launch, from two rocprofv3 --pmc
 # passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean over the dispatches
 # of one solve) scaled by what the counters read for a 256 MiB copy
-# (FETCH_SIZE reads 0.5001 of the bytes read, WRITE_SIZE 1.0 of the bytes
-# written).  Keyed by (mode, kernel); valid only for the workload and precision measured
-# and while the sources of the kernel hash to the recorded value (otherwise
-# traffic is reported null).
+# (FETCH_SIZE reads 0.50008 of the bytes read, WRITE_SIZE 1.0 of the bytes
+# written).  Keyed by (mode, kernel, workload, precision); valid only while
+# the sources of the kernel hash to the recorded value (otherwise traffic is
+# reported null).
 TRAFFIC = {
-    ("treecode", "p2p"): {"workload": "sphere_81920", "precision": "mixed", "fetch_kib": 5843.61, "fetch_scale": 0.50006,
-                          "write_kib": 51638.60, "write_scale": 1.0, "sha": "486e9fb11d200fa2"},
-    ("direct", "p2p"): {"workload": "sphere_81920", "precision": "mixed", "fetch_kib": 20980.51, "fetch_scale": 0.50006,
-                        "write_kib": 33280.0, "write_scale": 1.0, "sha": "614bbeac61608d8e"},
+    ("treecode", "m2p", "globule_5000", "mixed"): {
+        "fetch_kib": 4612.76, "fetch_scale": 0.50008, "write_kib": 139723.00,
+        "write_scale": 1.0, "sha": "d7b0216f1432cb9e"},
+    ("treecode", "p2p", "globule_5000", "mixed"): {
+        "fetch_kib": 16974.85, "fetch_scale": 0.50008, "write_kib": 198625.44,
+        "write_scale": 1.0, "sha": "d7b0216f1432cb9e"},
 }
 TRAFFIC_SOURCES = {
-    ("treecode", "p2p"): ["k_tree.hip", "pair.hpp", "tree.hpp", "k_treebuild.hip"],
-    ("direct", "p2p"): ["k_p2p.hip", "pair.hpp"],
+    "treecode": ["k_tree.hip", "pair.hpp", "tree.hpp", "k_treebuild.hip"],
+    "direct": ["k_p2p.hip", "pair.hpp"],
 }
 
 
@@ -66,12 +68,12 @@ def _sources_hash(files):
 
 
 def traffic_bytes(mode, kernel, workload, precision):
-    rec = TRAFFIC.get((mode, kernel))
-    if rec is None or rec["workload"] != workload or rec["precision"] != precision:
-        return None
-    if rec["sha"] != _sources_hash(TRAFFIC_SOURCES[(mode, kernel)]):
+    rec = TRAFFIC.get((mode, kernel, workload, precision))
+    if rec is None or rec["sha"] != _sources_hash(TRAFFIC_SOURCES[mode]):
         return None
     return rec["fetch_kib"] * 1024 / rec["fetch_scale"] + rec["write_kib"] * 1024 / rec["write_scale"]
+
+
 ALG_FLOP_PER_PAIR = 33  # four kernels per (target, far-field node) pair
 PEAK_FP32_VECTOR = 157.3  # TFLOP/s, MI355X published (packed FP32)
 PEAK_FP32_NONPACKED = 78.6  # nominal: 256 CU x 64 lanes x 2 FLOP x 2.4 GHz

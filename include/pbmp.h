@@ -102,6 +102,10 @@ typedef struct pbmp_options {
                            in finite differences or dynamics, and a backward
                            starts its transposed loops from the previous
                            backward's multipliers; 0: from zero */
+  int verbose;          /* nonzero: one line on stderr per induced-dipole
+                           iteration of a solve or backward (state,
+                           iteration, GMRES steps, change, seconds since the
+                           call began), as progress for long solves       */
 } pbmp_options;
 
 typedef struct pbmp_ctx pbmp_ctx;
@@ -142,7 +146,7 @@ typedef struct pbmp_result {
 /* Fill `o` with defaults: eps 1/80, kappa 0.125, 3 far nodes, eta 2,
  * AUTO mode, theta 0.5, P 4, leaf 300, GMRES(50) tol 1e-6 maxit 1000,
  * SCF tol 1e-6 D, omega 0.7, maxit 200, Thole a 0.39, MIXED, NULL stream,
- * no warm start. */
+ * no warm start, not verbose. */
 void pbmp_default_options(pbmp_options *o);
 
 /* Create a context on the current HIP device for one dielectric problem of
@@ -159,7 +163,7 @@ int pbmp_create(const pbmp_options *o, pbmp_ctx **out);
  * GMRES and self-consistent-loop settings of sections "The boundary element
  * method" and "Self-consistent induced field", and the precision):
  * gmres_restart, gmres_tol, gmres_maxit, scf_tol_debye, scf_omega,
- * scf_maxit, warm_start and precision are taken from *o (range-checked as
+ * scf_maxit, warm_start, verbose and precision are taken from *o (range-checked as
  * in pbmp_create); every other field must equal the context's (PBMP_EARG
  * otherwise: the discretisation is fixed at creation).  A precision change
  * keeps the last solution, so a backward may run at another precision than

@@ -52,6 +52,7 @@ void pbmp_default_options(pbmp_options *o) {
   o->precision = PBMP_MIXED;
   o->hip_stream = nullptr;
   o->warm_start = 0;
+  o->verbose = 0;
 }
 
 int pbmp_create(const pbmp_options *o, pbmp_ctx **out) {

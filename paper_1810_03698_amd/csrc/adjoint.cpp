@@ -15,7 +15,9 @@
 // iteration matrix is the transpose of the forward one), each dissolved
 // step with GMRES on A^T.  The gradient is the explicit derivative of the
 // Lagrangian at fixed states.
+#include <chrono>
 #include <cmath>
+#include <cstdio>
 
 #include "runtime.hpp"
 
@@ -120,18 +122,19 @@ int Runtime::backward(double dGbar, double *g_xyz, double *g_q, double *g_d, dou
   // only the accuracy asked of the gradient, not that of the forward solve
   const double rel_tol = std::min(1e-7, std::max(1e-11, 0.1 * o.gmres_tol));
   int warn = 0;
+  const auto t_start = std::chrono::steady_clock::now();
   auto relax = [&](bool dissolved, Dbuf<double> &lam, Dbuf<double> &w) {
     if (!warm) {
       PBMP_HIP(hipMemsetAsync(lam.p, 0, sizeof(double) * 3 * M, s_));
       if (dissolved) PBMP_HIP(hipMemsetAsync(lx.p, 0, sizeof(double) * 2 * N, s_));
     }
     for (int it = 1; it <= o.scf_maxit; ++it) {
+      int gi = 0;
       launch_scale_sites(s_, M, salpha_.p, lam.p, w.p);
       if (dissolved) {
         launch_make_weights(s_, M, c, sq_.p, sd_.p, sQ_.p, w.p, Wp.p);
         launch_readout_T(s_, N, M, src64_.p, geo_.p, verts_.p, tri_.p, ru_, sxyz_.p, Wp.p,
                          tsrow_.p, tscol_.p, rhs.p);
-        int gi = 0;
         const int rc = gmres(rhs.p, lx.p, true, &gi);
         if (rc > 0) warn = rc;
         launch_scale(s_, N, 1.0 / (4.0 * M_PI * eps), lx.p, sig.p);
@@ -143,6 +146,12 @@ int Runtime::backward(double dGbar, double *g_xyz, double *g_q, double *g_d, dou
       double h[2];
       PBMP_HIP(hipMemcpyAsync(h, red.p, sizeof(h), hipMemcpyDeviceToHost, s_));
       sync();
+      if (o.verbose)
+        std::fprintf(stderr, "pbmp backward: %s iteration %d gmres %d change %.3e %.1f s\n",
+                     dissolved ? "dissolved" : "vacuum", it, gi,
+                     h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : 0.0,
+                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start)
+                         .count());
       if (!std::isfinite(h[0])) throw Error(PBMP_WSCF, "adjoint iteration diverged");
       if (std::sqrt(h[0]) <= rel_tol * std::sqrt(h[1]) || h[1] == 0.0) {
         launch_scale_sites(s_, M, salpha_.p, lam.p, w.p);

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <functional>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 
@@ -237,6 +238,7 @@ void Runtime::set_options(const pbmp_options &n) {
   o.scf_omega = n.scf_omega;
   o.scf_maxit = n.scf_maxit;
   o.warm_start = n.warm_start;
+  o.verbose = n.verbose;
   if (outer_) {
     outer_->o.gmres_restart = n.gmres_restart;
     outer_->o.gmres_tol = n.gmres_tol;
@@ -876,6 +878,7 @@ void Runtime::readout(const double *x, bool full, double *out) {
 // ----------------------------------------------------------------- SCF
 int Runtime::scf(bool solvent, double *mu, int *gm_warn) {
   const int M = M_, N = N_;
+  const auto t_start = clk::now();
   const double dbye = debye_per_e_ang();
   // warm start: keep the previous solve's dipoles and surface solution
   const bool warm = o.warm_start && warm_ok_;
@@ -890,11 +893,11 @@ int Runtime::scf(bool solvent, double *mu, int *gm_warn) {
     }
   }
   for (int it = 1; it <= o.scf_maxit; ++it) {
+    int gi = 0;
     if (solvent) {
       launch_scale(s_, 3 * M, 1.0, sd_.p, p_.p);
       launch_axpy(s_, 3 * M, 1.0, mu, p_.p);
       launch_rhs(s_, fp64(), N, M, geo_.p, sxyz_.p, sq_.p, p_.p, sQ_.p, o.eps_in, b_.p);
-      int gi = 0;
       auto tm = clk::now();
       const int rc = outer_ ? gmres_stern(b_.p, x_.p, &gi) : gmres(b_.p, x_.p, false, &gi);
       t_matvec_ms_ += ms_since(tm);
@@ -908,6 +911,9 @@ int Runtime::scf(bool solvent, double *mu, int *gm_warn) {
     PBMP_HIP(hipMemcpyAsync(&d2, dmu2_.p, sizeof(double), hipMemcpyDeviceToHost, s_));
     sync();
     const double rms = std::sqrt(d2 / M) * dbye;
+    if (o.verbose)
+      std::fprintf(stderr, "pbmp solve: %s iteration %d gmres %d rms change %.3e D %.1f s\n",
+                   solvent ? "dissolved" : "vacuum", it, gi, rms, 1e-3 * ms_since(t_start));
     if (!std::isfinite(rms)) throw Error(PBMP_WSCF, "induced dipoles diverged");
     if (rms < o.scf_tol_debye) return it;
   }

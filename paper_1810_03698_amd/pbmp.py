@@ -33,7 +33,7 @@ class Options(ctypes.Structure):
                 ("scf_tol_debye", ctypes.c_double), ("scf_omega", ctypes.c_double),
                 ("scf_maxit", ctypes.c_int), ("thole_a", ctypes.c_double),
                 ("precision", ctypes.c_int), ("hip_stream", ctypes.c_void_p),
-                ("warm_start", ctypes.c_int)]
+                ("warm_start", ctypes.c_int), ("verbose", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
@@ -177,7 +177,7 @@ class Solver:
                  leaf_panels=300, gmres_restart=50, gmres_tol=1e-6,
                  gmres_maxit=1000, scf_tol_debye=1e-6, scf_omega=0.7,
                  scf_maxit=200, thole_a=0.39, precision="mixed", stream=None,
-                 warm_start=False):
+                 warm_start=False, verbose=False):
         self.lib = load()
         o = Options()
         self.lib.pbmp_default_options(ctypes.byref(o))
@@ -191,6 +191,7 @@ class Solver:
         o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
         o.hip_stream = stream
         o.warm_start = int(bool(warm_start))
+        o.verbose = int(bool(verbose))
         self.opts = o
         ctx = ctypes.c_void_p()
         rc = self.lib.pbmp_create(ctypes.byref(o), ctypes.byref(ctx))
@@ -231,16 +232,17 @@ class Solver:
     def set_options(self, **kw):
         """Change solver settings between solves (gmres_restart, gmres_tol,
         gmres_maxit, scf_tol_debye, scf_omega, scf_maxit, warm_start,
-        precision)."""
+        verbose, precision)."""
         o = self.opts
         for k, v in kw.items():
             if k not in ("gmres_restart", "gmres_tol", "gmres_maxit", "scf_tol_debye",
-                         "scf_omega", "scf_maxit", "warm_start", "precision"):
+                         "scf_omega", "scf_maxit", "warm_start", "verbose",
+                         "precision"):
                 raise ValueError("%s is fixed at creation" % k)
             if k == "precision":
                 v = PRECISION[v] if isinstance(v, str) else int(v)
             setattr(o, k, int(v) if k in ("gmres_restart", "gmres_maxit", "scf_maxit",
-                                          "warm_start", "precision") else float(v))
+                                          "warm_start", "verbose", "precision") else float(v))
         self._check(self.lib.pbmp_set_options(self.ctx, ctypes.byref(o)))
 
     def set_stern(self, verts, tris, eps_stern):

@@ -65,6 +65,7 @@ def test_default_options(lib):
     assert (o.gmres_restart, o.gmres_tol) == (50, 1e-6)
     assert (o.scf_tol_debye, o.scf_omega, o.thole_a) == (1e-6, 0.7, 0.39)
     assert o.precision == 1 and o.hip_stream is None
+    assert o.warm_start == 0 and o.verbose == 0
 
 
 def test_product_path_has_no_oracle_dependency():

@@ -41,12 +41,14 @@ def test_m2p_flops():
 
 
 def test_traffic_only_for_the_measured_case():
-    for mode, lo, hi in (("treecode", 6e7, 7e7), ("direct", 7e7, 8e7)):
-        rec = bench.TRAFFIC[(mode, "p2p")]
-        current = rec["sha"] == bench._sources_hash(bench.TRAFFIC_SOURCES[(mode, "p2p")])
-        t = bench.traffic_bytes(mode, "p2p", rec["workload"], rec["precision"])
+    for (mode, kernel, workload, precision), rec in bench.TRAFFIC.items():
+        current = rec["sha"] == bench._sources_hash(bench.TRAFFIC_SOURCES[mode])
+        t = bench.traffic_bytes(mode, kernel, workload, precision)
         # recorded counters hold only while the kernel's sources are unchanged
-        assert (t is not None and lo < t < hi) if current else t is None
-        assert bench.traffic_bytes(mode, "p2p", "globule_5000", rec["precision"]) is None
-        assert bench.traffic_bytes(mode, "p2p", rec["workload"], "fp64") is None
-    assert bench.traffic_bytes("treecode", "m2p", "sphere_81920", "mixed") is None
+        if current:
+            assert t is not None and 1e8 < t < 3e8
+        else:
+            assert t is None
+        assert bench.traffic_bytes(mode, kernel, "sphere_81920", precision) is None
+        assert bench.traffic_bytes(mode, kernel, workload, "fp64") is None
+    assert bench.traffic_bytes("direct", "p2p", "globule_5000", "mixed") is None

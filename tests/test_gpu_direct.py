@@ -229,3 +229,22 @@ def test_nonconvergence_warnings(cfg0):
     assert s.solve()["status"] == 1
     s = _solver(cfg0, scf_maxit=1)
     assert s.solve()["status"] == 2
+
+
+def test_verbose_progress_lines(cfg0, capfd):
+    """verbose: one stderr line per induced-dipole iteration, the vacuum
+    state first, with the solve's own iteration counts."""
+    s = _solver(cfg0, verbose=True, scf_tol_debye=1e-6)
+    r = s.solve(outputs=False)
+    s.set_options(verbose=False)
+    s.solve(outputs=False)
+    s.close()
+    lines = [l for l in capfd.readouterr().err.splitlines() if l.startswith("pbmp solve:")]
+    vac = [l for l in lines if " vacuum " in l]
+    diss = [l for l in lines if " dissolved " in l]
+    assert len(vac) == r["scf_iters_vac"] and len(diss) == r["scf_iters"]
+    assert lines[:len(vac)] == vac
+    # Arnoldi steps used per solve; the total also counts the steps the
+    # pipelined loop enqueued past convergence
+    used = sum(int(l.split(" gmres ")[1].split()[0]) for l in diss)
+    assert 0 < used <= r["gmres_iters"]
