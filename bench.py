@@ -412,9 +412,11 @@ def main():
     achieved = per_launch / (avg_ms * 1e-3) / 1e12
     # the far field runs in FP32 in mixed precision and in FP64 otherwise
     peak = PEAK_FP32_VECTOR if args.precision == "mixed" else PEAK_FP64_VECTOR
+    traffic = traffic_bytes(mode, name, args.workload, args.precision)
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak,
                 "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": traffic_bytes(mode, name, args.workload, args.precision), "traffic_unit": "bytes per launch",
+                "traffic": traffic, "traffic_unit": "bytes per launch",
+                "traffic_rate_GBps": (traffic / (avg_ms * 1e-3) / 1e9 if traffic else None),
                 "kernel": name, "avg_launch_ms": avg_ms,
                 "frac_of_nonpacked_fp32": (achieved / PEAK_FP32_NONPACKED
                                            if args.precision == "mixed" else None),
