@@ -418,7 +418,10 @@ def test_binding_triad_fullsize(say):
     than on the energy: on the small triad of test_gpu_binding it is 8e-3
     of the gradient's norm at P 4 and 1e-3 at P 5 (against the direct-mode
     gradient; energies 3e-5 and 9e-6), and here the difference to direct
-    solves is 4e-3 (x axis; bar 1e-2 of the gradient's norm).  The
+    solves is 4e-3 (x axis; bar 1e-2 of the gradient's norm).  The error
+    falls with theta and P (small triad: 1.8e-5 at theta 0.3, P 6; a
+    theta 0.3, P 6 solve and backward of this complex take over 15 minutes
+    in FP64, beyond one run).  The
     displaced solves are FP64 (the mixed path's FP32 far readout leaves the
     induced dipoles a noise floor near 6e-9 D, above the 1e-9 D these
     differences need) and take about four minutes each, so PBMP_LONG_AXES
