@@ -103,12 +103,11 @@ __device__ inline void node_kernels(T X, T Y, T Z, T nx, T ny, T nz, T nR,
   const T i5 = i3 * i2;
   const T R[3] = {X, Y, Z};
   const T n[3] = {nx, ny, nz};
-  const T t5 = T(3) * nR * i5;
   g[0] += i1;
   h[0] += nR * i3;
   for (int a = 0; a < 3; ++a) {
     g[1 + a] -= R[a] * i3;
-    h[1 + a] += n[a] * i3 - t5 * R[a];
+    h[1 + a] += n[a] * i3 - T(3) * nR * R[a] * i5;
   }
   if constexpr (FULL) {
     const T i7 = i5 * i2;
@@ -127,28 +126,21 @@ __device__ inline void node_kernels(T X, T Y, T Z, T nx, T ny, T nz, T nR,
 // Far-field readout: one site per lane (64 sites per block), the panels of
 // one source chunk staged through LDS in tiles of kRoTile records (coalesced
 // 16-byte loads of the contiguous records, all issued before the first
-// store), per-chunk partial sums part[chunk][site][k].  FP64: node
-// differences, kernels and sums in FP64.  Mixed: the tile's nodes are
-// stored in FP32 relative to the tile's first node o (computed once per
-// tile from the FP64 positions: a tile of Morton-ordered panels spans a few
-// A, so the offsets lose nothing), each lane forms its site's offset P - o
-// once per tile, and the differences (P - o) - (y - o) are FP32; the
-// kernels and the strength-weighted sums are FP32 within a tile and folded
-// into FP64 accumulators per tile.
+// store), per-chunk partial sums part[chunk][site][k].  Per panel the sums
+// are formed as in the operator: node differences from FP64 positions, the
+// kernels in T, the panel's strengths applied before the FP64 accumulation.
 constexpr int kRoTile = 64;
 
-template <bool FP64, bool FULL, int NF>
+template <bool FP64, bool FULL>
 __global__ __launch_bounds__(64) void k_readout_far(
-    int N, int M, const double *__restrict__ src64,
+    int N, int M, int nf, const double *__restrict__ src64,
     const float *__restrict__ src32, const double *__restrict__ xyz, int chunk,
     double *__restrict__ part) {
   constexpr int NO = FULL ? 10 : 4;
-  constexpr int nf = NF;
   typedef double d2 __attribute__((ext_vector_type(2)));
   typedef float f4 __attribute__((ext_vector_type(4)));
   __shared__ __align__(16) double s64[kRoTile * 16];
   __shared__ __align__(16) float s32[FP64 ? 4 : kRoTile * 16];
-  __shared__ float srel[FP64 ? 4 : kRoTile * 9];  // node offsets from the tile origin
   const int lane = (int)threadIdx.x;
   const int l = blockIdx.x * 64 + lane;
   const int lc = min(l, M - 1);
@@ -192,46 +184,30 @@ __global__ __launch_bounds__(64) void k_readout_far(
       }
     }
     __syncthreads();
-    if constexpr (FP64) {
-      for (int jj = 0; jj < nj; ++jj) {
-        const double *r64 = s64 + 16 * jj;
+    for (int jj = 0; jj < nj; ++jj) {
+      const double *r64 = s64 + 16 * jj;
+      if constexpr (FP64) {
         double g[NO], h[NO];
         for (int k = 0; k < NO; ++k) g[k] = h[k] = 0.0;
         const double nR = r64[9] * P[0] + r64[10] * P[1] + r64[11] * P[2] - r64[12];
-#pragma unroll
         for (int qn = 0; qn < nf; ++qn)
           node_kernels<double, FULL>(P[0] - r64[3 * qn], P[1] - r64[3 * qn + 1],
                                      P[2] - r64[3 * qn + 2], r64[9], r64[10], r64[11],
                                      nR, g, h);
         for (int k = 0; k < NO; ++k) acc[k] += r64[13] * g[k] - r64[14] * h[k];
-      }
-    } else {
-      // node offsets from the tile origin o (the tile's first node), one
-      // panel per lane
-      const double o[3] = {s64[0], s64[1], s64[2]};
-      if (lane < nj)
-        for (int qn = 0; qn < nf; ++qn)
-          for (int d = 0; d < 3; ++d)
-            srel[9 * lane + 3 * qn + d] = (float)(s64[16 * lane + 3 * qn + d] - o[d]);
-      __syncthreads();
-      const float Po[3] = {(float)(P[0] - o[0]), (float)(P[1] - o[1]), (float)(P[2] - o[2])};
-      float a32[NO];
-      for (int k = 0; k < NO; ++k) a32[k] = 0.0f;
-      for (int jj = 0; jj < nj; ++jj) {
+      } else {
         const float *r = s32 + 16 * jj;
-        const float *y = srel + 9 * jj;
         float g[NO], h[NO];
         for (int k = 0; k < NO; ++k) g[k] = h[k] = 0.0f;
-        // n.(P - y0): the nodes of a flat panel share its plane
-        const float X0 = Po[0] - y[0], Y0 = Po[1] - y[1], Z0 = Po[2] - y[2];
-        const float nR = fmaf(r[9], X0, fmaf(r[10], Y0, r[11] * Z0));
-#pragma unroll
+        const float nR = (float)(r64[9] * P[0] + r64[10] * P[1] + r64[11] * P[2] - r64[12]);
         for (int qn = 0; qn < nf; ++qn)
-          node_kernels<float, FULL>(Po[0] - y[3 * qn], Po[1] - y[3 * qn + 1],
-                                    Po[2] - y[3 * qn + 2], r[9], r[10], r[11], nR, g, h);
-        for (int k = 0; k < NO; ++k) a32[k] = fmaf(r[13], g[k], fmaf(-r[14], h[k], a32[k]));
+          node_kernels<float, FULL>((float)(P[0] - r64[3 * qn]),
+                                    (float)(P[1] - r64[3 * qn + 1]),
+                                    (float)(P[2] - r64[3 * qn + 2]), r[9], r[10],
+                                    r[11], nR, g, h);
+        for (int k = 0; k < NO; ++k)
+          acc[k] += (double)(r[13] * g[k] - r[14] * h[k]);
       }
-      for (int k = 0; k < NO; ++k) acc[k] += (double)a32[k];
     }
   }
   if (l < M)
@@ -534,22 +510,13 @@ void launch_readout(hipStream_t s, bool fp64, bool full, int N, int M,
   if (M <= 0) return;
   const int chunk = (N + nchunk - 1) / nchunk;
   dim3 grid((M + 63) / 64, nchunk);
-#define PBMP_RO(F64, FULL)                                                            \
-  if (ru.nf == 3)                                                                     \
-    hipLaunchKernelGGL((k_readout_far<F64, FULL, 3>), grid, dim3(64), 0, s, N, M, src64, \
-                       src32, xyz, chunk, part);                                        \
-  else                                                                                \
-    hipLaunchKernelGGL((k_readout_far<F64, FULL, 1>), grid, dim3(64), 0, s, N, M, src64, \
-                       src32, xyz, chunk, part)
-  if (fp64 && full) {
-    PBMP_RO(true, true);
-  } else if (fp64) {
-    PBMP_RO(true, false);
-  } else if (full) {
-    PBMP_RO(false, true);
-  } else {
-    PBMP_RO(false, false);
-  }
+#define PBMP_RO(F64, FULL)                                                   \
+  hipLaunchKernelGGL((k_readout_far<F64, FULL>), grid, dim3(64), 0, s, N, M, \
+                     ru.nf, src64, src32, xyz, chunk, part)
+  if (fp64 && full) PBMP_RO(true, true);
+  else if (fp64) PBMP_RO(true, false);
+  else if (full) PBMP_RO(false, true);
+  else PBMP_RO(false, false);
 #undef PBMP_RO
   PBMP_HIP(hipGetLastError());
   if (full)
