@@ -88,6 +88,26 @@ int main() {
         "null context set_mesh");
   check(pbmp_site_fields(nullptr, nullptr, nullptr, PBMP_HOST) == PBMP_EARG,
         "null context site_fields");
+  check(pbmp_site_fields_noalloc(nullptr, nullptr, nullptr) == PBMP_EARG,
+        "null context site_fields_noalloc");
+  check(pbmp_set_options(nullptr, &o) == PBMP_EARG, "null context set_options");
+  check(pbmp_matvec(nullptr, nullptr, nullptr, 0, PBMP_HOST) == PBMP_EARG,
+        "null context matvec");
+  check(pbmp_rhs(nullptr, nullptr, nullptr, PBMP_HOST) == PBMP_EARG, "null context rhs");
+  check(pbmp_backward(nullptr, 1.0, nullptr, nullptr, nullptr, nullptr, nullptr, PBMP_HOST) ==
+            PBMP_EARG,
+        "null context backward");
+  check(pbmp_kernel_stats(nullptr, 0, nullptr) == PBMP_EARG, "null context kernel_stats");
+  {
+    double out3[3];
+    check(pbmp_binding_energies(nullptr, nullptr, nullptr, out3) == PBMP_EARG,
+          "null contexts binding_energies");
+    int64_t nlv = 0;
+    check(pbmp_ligand_translation_gradient(nullptr, 0, nullptr, out3, &nlv, PBMP_HOST) ==
+              PBMP_EARG,
+          "null context ligand_translation_gradient");
+  }
+  check(std::strlen(pbmp_last_error(nullptr)) > 0, "last_error without a context");
   pbmp_destroy(nullptr);
 
   // valid options: the quadrature rules are set up, then the first HIP call
