@@ -70,3 +70,36 @@ def test_small_molecule_mesh():
         assert abs(2 * np.arctan2(num, den).sum() / (4 * np.pi) - 1) < 1e-9
     rg = np.sqrt(((pos - pos.mean(0)) ** 2).sum(1).mean())
     assert abs(rg - 5.0) < 0.5
+
+
+def test_globule_recipe():
+    """The 1000-atom globule as its workload states it: about 30k panels of a
+    closed outward surface, radius of gyration about 14 A, radii in
+    [1.2, 2.0] A, every site inside, multipole and polarisability ranges of
+    the sphere workloads, treecode theta 0.5 and P 4."""
+    w = workload("globule_1000", cache=False)
+    assert len(w["xyz"]) == 1000 and 25000 <= len(w["tris"]) <= 35000
+    _check_closed_outward(w["verts"], w["tris"])
+    x = w["xyz"]
+    rg = np.sqrt(((x - x.mean(0)) ** 2).sum(1).mean())
+    assert abs(rg - 14.0) < 0.5
+    assert w["radii"].min() >= 1.2 and w["radii"].max() <= 2.0
+    assert (np.abs(w["q"]) <= 0.5).all() and (np.linalg.norm(w["d"], axis=1) <= 0.3).all()
+    assert ((w["alpha"] >= 0.3) & (w["alpha"] <= 1.5)).all()
+    p = w["params"]
+    assert (p["mode"], p["theta"], int(p["order_P"])) == ("treecode", 0.5, 4)
+
+
+def test_binding_triad_recipe():
+    """The binding triad: the ligand sits at a 3.5 A gap between atom spheres
+    from the receptor, the complex's sites are the receptor's followed by the
+    ligand's, and the three surfaces have about 90k, 8k and 95k panels."""
+    R, L, C = (workload(n, cache=False) for n in ("binding_receptor", "binding_ligand",
+                                                   "binding_complex"))
+    dd = np.linalg.norm(R["xyz"][:, None, :] - L["xyz"][None], axis=2)
+    gap = (dd - R["radii"][:, None] - L["radii"][None, :]).min()
+    assert abs(gap - 3.5) < 1e-6
+    assert int(C["n_receptor"]) == len(R["xyz"]) == 3000 and len(L["xyz"]) == 200
+    assert np.array_equal(C["xyz"], np.concatenate([R["xyz"], L["xyz"]]))
+    for w, n in ((R, 90000), (L, 8000), (C, 95000)):
+        assert abs(len(w["tris"]) - n) < 0.1 * n
