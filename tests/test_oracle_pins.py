@@ -3,6 +3,7 @@ mathematics (closed forms, identities, brute force, library routines).
 CPU only."""
 
 import math
+import os
 
 import numpy as np
 import pytest
@@ -11,6 +12,8 @@ from scipy import integrate
 
 from oracle import bie, kirkwood, multipoles as mp, quadrature, solver
 from synth import icosphere, workload
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 # ---------------------------------------------------------------- quadrature
@@ -50,16 +53,14 @@ def test_nineteen_point_rule_degree_nine():
 def test_nineteen_point_rule_published_values():
     """The rule equals the published symmetric degree-9, 19-point rule
     (D. A. Dunavant, Int. J. Numer. Meth. Eng. 21 (1985) 1129, table for
-    degree 9; weights normalised to sum 1, values printed to 15 digits)."""
+    degree 9; weights normalised to sum 1, values printed to 15 digits),
+    stored as the fixture tests/golden/dunavant_degree9_19pt.txt."""
     b, w = quadrature.tri19()
-    printed = [  # (weight, barycentric node of one orbit member)
-        (0.097135796282799, (1 / 3, 1 / 3, 1 / 3)),
-        (0.031334700227139, (0.020634961602525, 0.489682519198738, 0.489682519198738)),
-        (0.077827541004774, (0.125820817014127, 0.437089591492937, 0.437089591492937)),
-        (0.079647738927210, (0.623592928761935, 0.188203535619033, 0.188203535619033)),
-        (0.025577675658698, (0.910540973211095, 0.044729513394453, 0.044729513394453)),
-        (0.043283539377289, (0.036838412054736, 0.221962989160766, 0.741198598784498)),
-    ]
+    rows = np.loadtxt(os.path.join(GOLDEN, "dunavant_degree9_19pt.txt"))
+    # (weight, barycentric node of one orbit member); the centroid is 1/3
+    # exactly, printed rounded
+    printed = [(r[0], (1 / 3, 1 / 3, 1 / 3) if k == 0 else tuple(r[1:]))
+               for k, r in enumerate(rows)]
     for wt, node in printed:
         d = np.abs(np.sort(b, axis=1) - np.sort(node)).max(axis=1)
         q = np.argmin(d)
